@@ -1,0 +1,343 @@
+"""FP64 CPU oracle of the path-guiding hot path (arXiv 2112.09728).
+
+TEST INFRASTRUCTURE ONLY: the parity tests, the smoke check and the CPU
+baseline of the benchmark load this module; the product path never does.
+The arithmetic lives in ``oracle.c``; this file only marshals numpy arrays into
+the C calls.  It imports nothing from the GPU package.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+NO_CLAMP = 1
+STRATEGY_NONE, STRATEGY_BRDF, STRATEGY_GUIDED, STRATEGY_GUIDED_NULL, STRATEGY_BRDF_NULL = range(5)
+
+
+class View(C.Structure):
+    _fields_ = [
+        ("width", C.c_int32), ("height", C.c_int32), ("pitch", C.c_int32),
+        ("normal", C.c_void_p), ("view_dir", C.c_void_p), ("depth", C.c_void_p),
+        ("roughness", C.c_void_p), ("albedo", C.c_void_p), ("motion", C.c_void_p),
+        ("disocc", C.c_void_p),
+    ]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("seed", C.c_uint64), ("frame", C.c_uint32), ("view", C.c_uint32),
+        ("k_max", C.c_int32), ("radius", C.c_int32),
+        ("pi_init", C.c_float), ("pi_lo", C.c_float), ("pi_hi", C.c_float),
+        ("eps_sigma", C.c_float), ("tau_depth", C.c_float), ("tau_normal", C.c_float),
+        ("rough_min", C.c_float), ("s_diffuse", C.c_float), ("f0", C.c_float),
+        ("flags", C.c_uint32),
+    ]
+
+
+class Rect(C.Structure):
+    _fields_ = [("x0", C.c_int32), ("y0", C.c_int32), ("x1", C.c_int32), ("y1", C.c_int32)]
+
+
+DEFAULTS = dict(k_max=16, radius=3, pi_init=0.05, pi_lo=0.05, pi_hi=0.95, eps_sigma=2.5e-4,
+                tau_depth=0.1, tau_normal=0.9, rough_min=0.1, s_diffuse=0.5, f0=0.04, flags=0)
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        _lib = C.CDLL(LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+def _declare(L):
+    P = C.c_void_p
+    i64, i32 = C.c_int64, C.c_int32
+    L.orc_philox4x32_10.argtypes = [P, P, P]
+    for name in ("orc_sq2hemi_n", "orc_hemi2sq_n"):
+        getattr(L, name).argtypes = [i64, P, P]
+    L.orc_onb_n.argtypes = [i64, P, P, P]
+    L.orc_brdf_f_n.argtypes = [i64, P, P, P, P, C.c_double, P]
+    L.orc_brdf_pdf_n.argtypes = [i64, P, P, P, C.c_double, P]
+    L.orc_brdf_sample_n.argtypes = [i64, P, P, C.c_double, P, P, P]
+    L.orc_gauss_pdf_sq_n.argtypes = [P, C.c_double, i64, P, P]
+    L.orc_gauss_sample_n.argtypes = [P, C.c_double, i64, P, P]
+    L.orc_guide_pdf_n.argtypes = [P, C.c_double, i64, P, P]
+    L.orc_batch_stats.argtypes = [i64, P, P, P, P]
+    L.orc_merge.argtypes = [P, P, P, P]
+    L.orc_training_set.argtypes = [P, P, i32, P, i32, i32, i32, P, P, P, i32]
+    L.orc_training_set.restype = i32
+    L.orc_reproject.argtypes = [P, P, P, P, P, P, Rect]
+    L.orc_sample.argtypes = [P, P, P, i32, P, P, P, P, P, Rect]
+    L.orc_pdf.argtypes = [P, P, P, i32, P, P, P, P, Rect]
+    L.orc_light.argtypes = [i32, P, C.c_double, P, i32, i32, i32, i32, P, P, P, Rect]
+    L.orc_em.argtypes = [P, P, i32, P, P, P, P, P, i32, i32, Rect]
+    L.orc_nll.argtypes = [P, P, i32, P, P, P, P, P, P, P, P, Rect]
+    L.orc_num_threads.restype = i32
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def params(seed, frame=0, view=0, **kw):
+    d = dict(DEFAULTS)
+    d.update(kw)
+    return Params(seed=seed, frame=frame, view=view, **d)
+
+
+class OView:
+    """Host arrays of one view, held alive for the C calls ([c][H][W] float32)."""
+
+    def __init__(self, scene, motion=None, disocc=None):
+        self.normal = _f32(scene["normal"])
+        self.view_dir = _f32(scene["view_dir"])
+        self.depth = _f32(scene["depth"])
+        self.roughness = _f32(scene["roughness"])
+        self.albedo = _f32(scene["albedo"])
+        self.motion = None if motion is None else _f32(motion)
+        self.disocc = None if disocc is None else np.ascontiguousarray(disocc, dtype=np.uint8)
+        self.height, self.width = self.depth.shape[-2:]
+        self.c = View(self.width, self.height, self.width, _ptr(self.normal), _ptr(self.view_dir),
+                      _ptr(self.depth), _ptr(self.roughness), _ptr(self.albedo),
+                      _ptr(self.motion), _ptr(self.disocc))
+
+
+def _rect(v, rect):
+    if rect is None:
+        return Rect(0, 0, v.width, v.height)
+    x0, y0, x1, y1 = rect
+    return Rect(x0, y0, x1, y1)
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def sq2hemi(u):
+    u = _f64(u).reshape(-1, 2)
+    w = np.zeros((u.shape[0], 3))
+    lib().orc_sq2hemi_n(u.shape[0], _ptr(u), _ptr(w))
+    return w
+
+
+def hemi2sq(w):
+    w = _f64(w).reshape(-1, 3)
+    u = np.zeros((w.shape[0], 2))
+    lib().orc_hemi2sq_n(w.shape[0], _ptr(w), _ptr(u))
+    return u
+
+
+def onb(n):
+    n = _f64(n).reshape(-1, 3)
+    t = np.zeros_like(n)
+    b = np.zeros_like(n)
+    lib().orc_onb_n(n.shape[0], _ptr(n), _ptr(t), _ptr(b))
+    return t, b
+
+
+def brdf_f(wo, wi, alpha, albedo, f0=0.04):
+    wo, wi = _f64(wo).reshape(-1, 3), _f64(wi).reshape(-1, 3)
+    n = wi.shape[0]
+    alpha = _f64(np.broadcast_to(alpha, (n,)))
+    albedo = _f64(np.broadcast_to(albedo, (n,)))
+    wo = _f64(np.broadcast_to(wo, (n, 3)))
+    out = np.zeros(n)
+    lib().orc_brdf_f_n(n, _ptr(wo), _ptr(wi), _ptr(alpha), _ptr(albedo), f0, _ptr(out))
+    return out
+
+
+def brdf_pdf(wo, wi, alpha, s_diffuse=0.5):
+    wi = _f64(wi).reshape(-1, 3)
+    n = wi.shape[0]
+    wo = _f64(np.broadcast_to(_f64(wo).reshape(-1, 3), (n, 3)))
+    alpha = _f64(np.broadcast_to(alpha, (n,)))
+    out = np.zeros(n)
+    lib().orc_brdf_pdf_n(n, _ptr(wo), _ptr(wi), _ptr(alpha), s_diffuse, _ptr(out))
+    return out
+
+
+def brdf_sample(wo, alpha, xi, s_diffuse=0.5):
+    xi = _f64(xi).reshape(-1, 3)
+    n = xi.shape[0]
+    wo = _f64(np.broadcast_to(_f64(wo).reshape(-1, 3), (n, 3)))
+    alpha = _f64(np.broadcast_to(alpha, (n,)))
+    wi = np.zeros((n, 3))
+    valid = np.zeros(n, np.int32)
+    lib().orc_brdf_sample_n(n, _ptr(wo), _ptr(alpha), s_diffuse, _ptr(xi), _ptr(wi), _ptr(valid))
+    return wi, valid.astype(bool)
+
+
+def gauss_pdf_sq(g5, u, eps=2.5e-4):
+    g5, u = _f64(g5), _f64(u).reshape(-1, 2)
+    out = np.zeros(u.shape[0])
+    lib().orc_gauss_pdf_sq_n(_ptr(g5), eps, u.shape[0], _ptr(u), _ptr(out))
+    return out
+
+
+def gauss_sample(g5, xi, eps=2.5e-4):
+    g5, xi = _f64(g5), _f64(xi).reshape(-1, 2)
+    u = np.zeros((xi.shape[0], 2))
+    lib().orc_gauss_sample_n(_ptr(g5), eps, xi.shape[0], _ptr(xi), _ptr(u))
+    return u
+
+
+def guide_pdf(g5, w, eps=2.5e-4):
+    g5, w = _f64(g5), _f64(w).reshape(-1, 3)
+    out = np.zeros(w.shape[0])
+    lib().orc_guide_pdf_n(_ptr(g5), eps, w.shape[0], _ptr(w), _ptr(out))
+    return out
+
+
+def batch_stats(u, w, gam):
+    u, w, gam = _f64(u).reshape(-1, 2), _f64(w), _f64(gam)
+    out = np.zeros(7)
+    lib().orc_batch_stats(u.shape[0], _ptr(u), _ptr(w), _ptr(gam), _ptr(out))
+    return out
+
+
+def merge(P, g_in, stats):
+    g_in, stats = _f64(g_in), _f64(stats)
+    out = np.zeros(8)
+    lib().orc_merge(C.byref(P), _ptr(g_in), _ptr(stats), _ptr(out))
+    return out
+
+
+def training_set(P, view, spp, strategy, x, y, k, cap=64):
+    strategy = np.ascontiguousarray(strategy, dtype=np.uint8)
+    q = np.zeros(cap, np.int32)
+    s = np.zeros(cap, np.int32)
+    keep = np.zeros(cap, np.int32)
+    n = lib().orc_training_set(C.byref(P), C.byref(view.c), spp, _ptr(strategy), x, y, k,
+                               _ptr(q), _ptr(s), _ptr(keep), cap)
+    return q[:n], s[:n], keep[:n].astype(bool)
+
+
+def reproject(P, cur, prev, gamma_prev, rect=None, out=None):
+    H, W = cur.height, cur.width
+    g_out = np.zeros((8, H, W)) if out is None else out
+    src = np.full((H, W), -2, np.int32)
+    gp = None if gamma_prev is None else _f64(gamma_prev)
+    lib().orc_reproject(C.byref(P), C.byref(cur.c), None if prev is None else C.byref(prev.c),
+                        _ptr(gp), _ptr(g_out), _ptr(src), _rect(cur, rect))
+    return g_out, src
+
+
+def sample(P, view, gamma, spp, rect=None):
+    H, W = view.height, view.width
+    gamma = _f64(gamma)
+    dir_ = np.zeros((3, spp, H, W))
+    pmix = np.zeros((spp, H, W))
+    pb = np.zeros((spp, H, W))
+    strat = np.zeros((spp, H, W), np.uint8)
+    margin = np.full((spp, H, W), np.inf)
+    lib().orc_sample(C.byref(P), C.byref(view.c), _ptr(gamma), spp, _ptr(dir_), _ptr(pmix),
+                     _ptr(pb), _ptr(strat), _ptr(margin), _rect(view, rect))
+    return dict(dir=dir_, pdf_mix=pmix, pdf_brdf=pb, strategy=strat, margin=margin)
+
+
+def pdf(P, view, gamma, dirs, rect=None):
+    """dirs: [3][n][H][W] world directions."""
+    H, W = view.height, view.width
+    dirs = _f64(dirs)
+    n = dirs.shape[1]
+    gamma = _f64(gamma)
+    pmix = np.zeros((n, H, W))
+    pg = np.zeros((n, H, W))
+    pb = np.zeros((n, H, W))
+    lib().orc_pdf(C.byref(P), C.byref(view.c), _ptr(gamma), n, _ptr(dirs), _ptr(pmix), _ptr(pg),
+                  _ptr(pb), _rect(view, rect))
+    return pmix, pg, pb
+
+
+def light(lights, ambient, vis, dirs, strategy, rect=None):
+    lights = _f32(lights)
+    vis = np.ascontiguousarray(vis, dtype=np.uint8)
+    dirs = _f64(dirs)
+    strategy = np.ascontiguousarray(strategy, dtype=np.uint8)
+    spp, H, W = strategy.shape
+    L = np.zeros((spp, H, W))
+    r = Rect(0, 0, W, H) if rect is None else Rect(*rect)
+    lib().orc_light(lights.shape[0], _ptr(lights), ambient, _ptr(vis), W, H, W, spp, _ptr(dirs),
+                    _ptr(strategy), _ptr(L), r)
+    return L
+
+
+def em(P, view, rec, gamma, iterations=1, batch=False, rect=None):
+    """Returns the updated state (the input array is not modified)."""
+    g = _f64(gamma).copy()
+    spp = rec["strategy"].shape[0]
+    d, pb = _f64(rec["dir"]), _f64(rec["pdf_brdf"])
+    st = np.ascontiguousarray(rec["strategy"], dtype=np.uint8)
+    L = _f64(rec["radiance"])
+    lib().orc_em(C.byref(P), C.byref(view.c), spp, _ptr(d), _ptr(pb), _ptr(st), _ptr(L), _ptr(g),
+                 iterations, int(bool(batch)), _rect(view, rect))
+    return g
+
+
+def nll(P, view, rec, theta, grad_out=None, rect=None):
+    H, W = view.height, view.width
+    spp = rec["strategy"].shape[0]
+    d, pb = _f64(rec["dir"]), _f64(rec["pdf_brdf"])
+    st = np.ascontiguousarray(rec["strategy"], dtype=np.uint8)
+    L = _f64(rec["radiance"])
+    th = _f64(theta)
+    go = None if grad_out is None else _f64(grad_out)
+    grad = np.zeros((8, H, W))
+    out = np.zeros((H, W))
+    lib().orc_nll(C.byref(P), C.byref(view.c), spp, _ptr(d), _ptr(pb), _ptr(st), _ptr(L),
+                  _ptr(th), _ptr(go), _ptr(grad), _ptr(out), _rect(view, rect))
+    return out, grad
+
+
+def num_threads():
+    return lib().orc_num_threads()
+
+
+class Frames:
+    """Plain frame sequence of the oracle: reproject -> sample -> light -> EM.
+
+    ``step`` returns the per-frame intermediates so a caller can compare them."""
+
+    def __init__(self, scene, seed, spp, view=0, **kw):
+        self.scene = scene
+        self.seed = seed
+        self.spp = spp
+        self.view_id = view
+        self.kw = kw
+        self.view_prev = None
+        self.gamma = None
+
+    def step(self, frame, motion=None, disocc=None, rect=None, gamma_prev=None):
+        v = OView(self.scene, motion, disocc)
+        P = params(self.seed, frame=frame, view=self.view_id, **self.kw)
+        gp = self.gamma if gamma_prev is None else gamma_prev
+        prev = self.view_prev if self.view_prev is not None else v
+        g1, src = reproject(P, v, prev, gp, rect=rect)
+        rec = sample(P, v, g1, self.spp, rect=rect)
+        rec["radiance"] = light(self.scene["lights"], float(self.scene["ambient"]), self.scene["vis"],
+                                rec["dir"], rec["strategy"], rect=rect)
+        g2 = em(P, v, rec, g1, rect=rect)
+        self.gamma = g2
+        self.view_prev = v
+        return dict(gamma_reproj=g1, src=src, rec=rec, gamma=g2)
