@@ -1,0 +1,241 @@
+"""Benchmark of the path-guiding hot path on one MI355X.
+
+One step = one frame of the 1920x1080, 1 spp, 64-frame workload with moving
+camera (motion U[-2,2] px, 2% disocclusion): reprojection + guided sampling
+(one fused launch), the analytic light field standing in for the trace (timed
+on its own, excluded from the metric), and the online EM update.  Frames
+0..warmup-1 run untimed, frames warmup..warmup+steps-1 are timed; the default
+8 + 56 covers the 64 frames of the workload.
+
+Prints one JSON line: ms/frame and Mpix/s of reproject+sample+EM, the HBM
+roofline of the dominant kernel and of the whole path, and the FP64 oracle's
+rate on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+# Algorithmic bytes per pixel-frame (G = bytes of Gamma per pixel, S = spp):
+#   fused reproject + sample: reads mv 8, mask 1, z 4, n 12, roughness 4,
+#     omega_o 12 at p; z_prev 4, n_prev 12, Gamma_prev G at the source q;
+#     writes Gamma' G and records 21 S (dir 12, D 4, p_b 4, strategy 1)
+#   EM: reads Gamma' G, n 12, omega_o 12, roughness 4, albedo 4 and records
+#     21 S (dir 12, L 4, p_b 4, strategy 1); writes Gamma G
+#   light field (not in the metric): reads dir 12 S, strategy S, vis 1;
+#     writes L 4 S
+
+
+def bytes_reproject_sample(G, S):
+    return 61 + 2 * G + 21 * S
+
+
+def bytes_em(G, S):
+    return 2 * G + 32 + 21 * S
+
+
+def bytes_light(S):
+    return 1 + 17 * S
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=56)
+    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--width", type=int, default=1920)
+    ap.add_argument("--height", type=int, default=1080)
+    ap.add_argument("--spp", type=int, default=1)
+    ap.add_argument("--gamma-dtype", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--unfused", action="store_true", help="reproject and sample as two launches")
+    ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0,
+                    help="budget of the oracle timing on the host (0 = skip)")
+    ap.add_argument("--seed", type=int, default=None)
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
+              "(the design for several GPUs is described, not built).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2112_09728_amd as pg
+    from paper_2112_09728_amd import workload as wl
+
+    pg.lib()  # fail loudly without the HIP library
+    cfg = wl.CONFIGS["1080p_spp1_64f_fp32_pan"]
+    seed = cfg["seed"] if a.seed is None else a.seed
+    W, H, S = a.width, a.height, a.spp
+    dt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[a.gamma_dtype]
+    G = 32 if a.gamma_dtype == "f32" else 16
+    frames = a.warmup + a.steps
+    t0 = time.time()
+    scene = wl.make_scene(W, H, seed)
+    mvs, masks = [], []
+    for t in range(frames):
+        mv, m = wl.make_motion(W, H, seed, t, moving=True)
+        mvs.append(torch.as_tensor(mv).cuda())
+        masks.append(torch.as_tensor(m).cuda())
+    guide = pg.Guide(scene, spp=S, seed=seed, gamma_dtype=dt, fused=not a.unfused)
+    views = [guide.view_for(mvs[t], masks[t]) for t in range(frames)]
+    torch.cuda.synchronize()
+    print(f"bench: setup {time.time() - t0:.1f} s ({W}x{H}, spp {S}, Gamma {a.gamma_dtype}, "
+          f"{frames} frames)", file=sys.stderr, flush=True)
+
+    def frame(t, ev=None):
+        p = guide.params(t)
+        cur = views[t]
+        prev = guide.prev_base if t > 0 else None
+        g_prev, g_out = guide.gamma[guide.cur], guide.gamma[1 - guide.cur]
+        if ev is not None:
+            ev[0].record()
+        if a.unfused:
+            pg.reproject(p, cur, prev, g_prev if t else None, g_out)
+            pg.sample_mis(p, cur, g_out, guide.samples)
+        else:
+            pg.reproject_sample(p, cur, prev, g_prev if t else None, g_out, guide.samples)
+        if ev is not None:
+            ev[1].record()
+        pg.light_field(guide.lights, cur, guide.vis, guide.samples)
+        if ev is not None:
+            ev[2].record()
+        pg.em_update(p, cur, guide.samples, g_out)
+        if ev is not None:
+            ev[3].record()
+        guide.cur = 1 - guide.cur
+
+    for t in range(a.warmup):
+        frame(t)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(a.steps)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for i in range(a.steps):
+        frame(a.warmup + i, evs[i])
+    end.record()
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(end)
+    rs = np.array([e[0].elapsed_time(e[1]) for e in evs])
+    lf = np.array([e[1].elapsed_time(e[2]) for e in evs])
+    em = np.array([e[2].elapsed_time(e[3]) for e in evs])
+    path = rs + em
+    ms = float(path.mean())
+    px = W * H
+    mpix = px / (ms * 1e-3) / 1e6
+    b_rs, b_em = bytes_reproject_sample(G, S), bytes_em(G, S)
+    b_path = b_rs + b_em
+    em_gbs = b_em * px / (em.mean() * 1e-3) / 1e9
+    rs_gbs = b_rs * px / (rs.mean() * 1e-3) / 1e9
+    path_gbs = b_path * px / (ms * 1e-3) / 1e9
+    dominant = "em" if em.mean() >= rs.mean() else "reproject_sample"
+    dom_gbs, dom_bytes = (em_gbs, b_em) if dominant == "em" else (rs_gbs, b_rs)
+    gk = guide.state
+    kmean = float(gk[7].float().mean())
+    print(f"bench: per frame reproject+sample {rs.mean() * 1e3:.1f} us, light {lf.mean() * 1e3:.1f} us, "
+          f"EM {em.mean() * 1e3:.1f} us (first timed {em[0] * 1e3:.1f}, last {em[-1] * 1e3:.1f}); "
+          f"wall {total_ms / a.steps * 1e3:.1f} us/frame; mean k at end {kmean:.2f}",
+          file=sys.stderr, flush=True)
+
+    cpu = None
+    if a.cpu_baseline_seconds > 0:
+        cpu = cpu_baseline(scene, seed, S, W, H, a.cpu_baseline_seconds)
+
+    out = {
+        "metric": "ms/frame & Mpix/s for reproject+sample+EM at 1080p 1spp; % of HBM roofline",
+        "value": round(mpix, 2),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{W}x{H} spp{S}, {frames}-frame moving-camera sequence "
+                        f"(timed frames {a.warmup}..{frames - 1}), Gamma {a.gamma_dtype}, "
+                        f"{'unfused' if a.unfused else 'fused reproject+sample'}",
+            "width": W, "height": H, "spp": S, "gamma_storage": a.gamma_dtype,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_em" if dominant == "em" else "k_reproject_sample",
+            "achieved": round(dom_gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "bytes_per_px": dom_bytes,
+            "us_per_launch": round(float((em if dominant == "em" else rs).mean()) * 1e3, 2),
+        },
+        "path_roofline": {
+            "bytes_per_px": b_path,
+            "achieved": round(path_gbs, 1),
+            "frac": round(path_gbs / HBM_PEAK_GBS, 4),
+            "reproject_sample_us": round(float(rs.mean()) * 1e3, 2),
+            "em_us": round(float(em.mean()) * 1e3, 2),
+            "light_field_us": round(float(lf.mean()) * 1e3, 2),
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(scene, seed, spp, W, H, budget_s):
+    """The FP64 oracle's reproject + sample + EM on the host cores (light field
+    excluded like on the GPU): whole frames of the same sequence from frame 0
+    until the time budget is spent."""
+    import oracle as O
+    from paper_2112_09728_amd import workload as wl
+
+    v_prev = None
+    gamma = None
+    spent = 0.0
+    n = 0
+    t_all = time.time()
+    while spent < budget_s and n < 64:
+        mv, mask = wl.make_motion(W, H, seed, n, moving=True)
+        v = O.OView(scene, mv, mask)
+        P = O.params(seed, frame=n)
+        t0 = time.time()
+        g1, _ = O.reproject(P, v, v_prev if v_prev is not None else v, gamma)
+        rec = O.sample(P, v, g1, spp)
+        t1 = time.time()
+        rec["radiance"] = O.light(scene["lights"], float(scene["ambient"]), scene["vis"], rec["dir"],
+                                  rec["strategy"])
+        t2 = time.time()
+        gamma = O.em(P, v, rec, g1)
+        t3 = time.time()
+        spent += (t1 - t0) + (t3 - t2)
+        v_prev = v
+        n += 1
+        print(f"bench: oracle frame {n - 1}: {((t1 - t0) + (t3 - t2)) * 1e3:.0f} ms", file=sys.stderr,
+              flush=True)
+    ms = spent / n * 1e3
+    return {
+        "value": round(W * H / (ms * 1e-3) / 1e6, 4),
+        "unit": "Mpix/s",
+        "ms_per_frame": round(ms, 1),
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": f"frames 0..{n - 1} of the same {W}x{H} spp{spp} sequence, whole frames "
+                  f"({time.time() - t_all:.0f} s wall incl. the untimed light field)",
+    }
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,222 @@
+/*
+ * libpmmguide: screen-space path guiding with per-pixel parametric mixture
+ * models on AMD Instinct MI355X (gfx950).
+ *
+ * Method: M. Derevyannykh, "Real-Time Path-Guiding Based on Parametric
+ * Mixture Models", arXiv 2112.09728.  Each pixel keeps a model Gamma of 8
+ * values (Abstract): a 2-D Gaussian N(mu, Sigma) on the unit square, carried to
+ * the hemisphere by the Shirley-Chiu area-preserving map M, mixed with the
+ * BRDF by a weight pi (Eq. (2)).  Per frame the library
+ *   1. reprojects Gamma from the previous frame through the motion vectors
+ *      with nearest-neighbour filtering and depth/normal rejection, and
+ *      re-expresses it in the current surface's hemisphere   (Sec. 3.1)
+ *   2. samples first-bounce directions: zeta < pi takes Box-Muller + N(mu,
+ *      Sigma) + M, otherwise the BRDF, and evaluates the one-sample MIS
+ *      density D of each direction                          (Sec. 3.1, Eq. (2))
+ *   3. trains Gamma by an online, radiance-weighted EM step from the pixel's
+ *      own and neighbouring BRDF-strategy samples          (Sec. 3.2, Sec. 4.2)
+ *
+ * Conventions shared by every call
+ *   - Every buffer is caller-owned DEVICE memory (e.g. a torch tensor's
+ *     data_ptr()), except the structs themselves and pg_lights, which are
+ *     read on the host during the call.  The library allocates nothing.
+ *   - Planes are row-major with row pitch `pitch` (elements).  Channel c of
+ *     pixel (x, y) of a [C][H*pitch] array is at c*H*pitch + y*pitch + x.
+ *   - Per-sample arrays hold sample s of pixel (x, y) at (s*H + y)*pitch + x;
+ *     the direction array has 3 such planes, [3][spp*H*pitch].
+ *   - Gamma has 8 planes [8][H*pitch] in the storage type of pg_gamma.dtype:
+ *       0 mu_x, 1 mu_y, 2 Sigma_xx, 3 Sigma_xy, 4 Sigma_yy, 5 pi, 6 W, 7 k
+ *     (k the training epoch, W the running evidence).  All arithmetic is
+ *     FP32 whatever the storage type; stores round to nearest-even and W
+ *     saturates at the format's largest finite value.
+ *   - Strategy codes: 0 no sample (omega_o below the surface), 1 BRDF
+ *     sample, 2 guided sample, 3 guided draw outside the unit square (null),
+ *     4 BRDF draw below the horizon (null).  Null samples record zeros.
+ *   - Calls enqueue work on `stream` (a hipStream_t; NULL = the null stream)
+ *     and return without synchronising.  Results are bit-identical run to
+ *     run and for every tile shape.
+ *   - Errors: argument problems are found on the host before any launch and
+ *     return PG_ERR_ARG (null required pointer, non-positive sizes, pitch <
+ *     width, spp outside [1, 8], unknown dtype, forbidden aliasing);
+ *     PG_ERR_UNSUPPORTED marks a valid request this build does not handle
+ *     (radius other than 3, sizes beyond the 32-bit index range); a failed
+ *     launch returns PG_ERR_HIP.  pg_last_error() then describes the error.
+ *     Numeric trouble is never an error: a non-finite history starts a new
+ *     model.
+ */
+#ifndef PMMGUIDE_H
+#define PMMGUIDE_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pg_status {
+  PG_OK = 0,
+  PG_ERR_ARG = 1,
+  PG_ERR_UNSUPPORTED = 2,
+  PG_ERR_HIP = 3
+} pg_status;
+
+typedef enum pg_dtype { PG_F32 = 0, PG_F16 = 1, PG_BF16 = 2 } pg_dtype;
+
+enum {
+  PG_NO_CLAMP = 1, /* do not clamp pi after the M-step                        */
+  PG_EM_BATCH = 2  /* pg_em_update: iterate plain batch EM on a fixed set     */
+};
+
+/* One view's G-buffer (Sec. 3.1 "rasterized G-Buffer"); all FP32 device planes. */
+typedef struct pg_view {
+  int32_t width, height, pitch;
+  const float *normal;    /* [3][H*pitch] shading normal, world space           */
+  const float *view_dir;  /* [3][H*pitch] omega_o, unit, towards the camera     */
+  const float *depth;     /* [H*pitch]                                          */
+  const float *roughness; /* [H*pitch]; GGX alpha = roughness^2                 */
+  const float *albedo;    /* [H*pitch] diffuse albedo                           */
+  const float *motion;    /* [2][H*pitch] px, current position minus previous;
+                             NULL = no motion                                   */
+  const uint8_t *disocc;  /* [H*pitch] nonzero = disoccluded; NULL = none       */
+} pg_view;
+
+/* Per-pixel model planes, [8][H*pitch] of the view they belong to. */
+typedef struct pg_gamma {
+  int32_t dtype; /* pg_dtype */
+  void *data;
+} pg_gamma;
+
+/* Sample records ("VPL" buffer Pi of Fig. 2, without the hit position). */
+typedef struct pg_samples {
+  int32_t spp;      /* samples per pixel, 1..8                                  */
+  float *dir;       /* [3][spp*H*pitch] world direction                         */
+  float *pdf_mix;   /* [spp*H*pitch] mixture density D(dir)                     */
+  float *pdf_brdf;  /* [spp*H*pitch] BRDF-sampling density p_b(dir)             */
+  uint8_t *strategy;/* [spp*H*pitch] strategy code                              */
+  float *radiance;  /* [spp*H*pitch] incident radiance along dir               */
+} pg_samples;
+
+/* Method constants and per-call counters.  pg_params_default() fills the
+ * values used throughout this library; the paper fixes pi_init = 0.05 and
+ * k = 0 for a new model (Sec. 3.1), the clamp [0.05, 0.95] (Sec. 3.2) and
+ * N(k) = (1 - k/kMax)*15 + 5 neighbour picks (Sec. 4.2); the others are this
+ * library's readings where the paper gives no value. */
+typedef struct pg_params {
+  uint64_t seed;    /* RNG key                                                   */
+  uint32_t frame;   /* frame index t: frame 0 starts every model anew            */
+  uint32_t view;    /* view index (RNG counter word)                             */
+  int32_t k_max;    /* kMax, 16                                                  */
+  int32_t radius;   /* neighbour window radius R, 3 (7x7 window)                 */
+  float pi_init;    /* 0.05                                                       */
+  float pi_lo, pi_hi; /* 0.05, 0.95                                               */
+  float eps_sigma;  /* covariance floor, 2.5e-4                                  */
+  float tau_depth;  /* reject if |z - z_prev| > tau_depth * z, 0.1              */
+  float tau_normal; /* reject if n . n_prev < tau_normal, 0.9                    */
+  float rough_min;  /* guide only if roughness >= rough_min, 0.1                 */
+  float s_diffuse;  /* probability of the cosine lobe in BRDF sampling, 0.5      */
+  float f0;         /* Schlick reflectance at normal incidence, 0.04             */
+  uint32_t flags;   /* PG_NO_CLAMP | PG_EM_BATCH                                  */
+  int32_t tile_w, tile_h; /* training tile; 0 = library default; results do not
+                             depend on it                                         */
+} pg_params;
+
+/* Analytic stand-in for the traced incident radiance (the paper traces rays,
+ * Fig. 2): L = ambient + sum_l V(p,l) c_l exp(lambda_l (w . xi_l - 1)). */
+#define PG_MAX_LIGHTS 8
+typedef struct pg_lights {
+  int32_t count;                  /* <= PG_MAX_LIGHTS                          */
+  float ambient;
+  float light[PG_MAX_LIGHTS][5];  /* axis xi (unit, world), lambda, c          */
+} pg_lights;
+
+/* Fill *p with the library's constants (seed 0, frame 0, view 0). */
+pg_status pg_params_default(pg_params *p);
+
+/* Reprojection of Gamma (Sec. 3.1: NN fetch through motion vectors,
+ * depth/normal stopping test, change of hemisphere; new model pi = 0.05,
+ * k = 0).  For pixel p the source is q = floor(p + 1/2 - motion(p)); the model
+ * restarts when frame == 0, p is disoccluded, q is outside the image,
+ * |z(p) - z_prev(q)| > tau_depth z(p), n(p).n_prev(q) < tau_normal, a
+ * channel of Gamma_prev(q) is not finite, or p is not guided (omega_o below
+ * the surface or roughness < rough_min).  Otherwise Gamma_prev(q) is copied
+ * and, when the normals differ, mu is moved so that M(mu) keeps its world
+ * direction (the model restarts if that direction is below p's horizon).
+ *   prev, prev_gamma: may be NULL only when frame == 0.
+ *   out_gamma must not alias prev_gamma; both use cur's height and pitch.
+ *   src_index (nullable) [H*pitch] int32: q.y*width_prev + q.x, or -1. */
+pg_status pg_reproject(const pg_params *p, const pg_view *cur, const pg_view *prev,
+                       pg_gamma prev_gamma, pg_gamma out_gamma, int32_t *src_index,
+                       void *stream);
+
+/* Guided sampling with one-sample MIS (Sec. 3.1 and Eq. (2)).  Sample s of
+ * pixel (x, y) draws four words of Philox4x32-10 with counter
+ * (y*width + x, frame, s, view) and key seed, giving zeta, xi_l, xi_1, xi_2
+ * as (word >> 8) * 2^-24.  With pi_eff = pi when k >= 1 and the pixel is
+ * guided (0 otherwise), zeta < pi_eff draws u = mu + L z (Box-Muller z,
+ * Cholesky L of Sigma + eps I) and w = M(u) (null if u leaves [0,1]^2);
+ * otherwise the BRDF is sampled with (xi_l, xi_1, xi_2).  Records the world
+ * direction, D(w) = pi_eff N(M^-1 w)/(2 pi) + (1 - pi_eff) p_b(w), p_b(w) and
+ * the strategy; out->radiance is not touched. */
+pg_status pg_sample_mis(const pg_params *p, const pg_view *v, pg_gamma gamma,
+                        const pg_samples *out, void *stream);
+
+/* pg_reproject followed by pg_sample_mis in one launch: writes out_gamma
+ * exactly as pg_reproject and the records exactly as pg_sample_mis would. */
+pg_status pg_reproject_sample(const pg_params *p, const pg_view *cur, const pg_view *prev,
+                              pg_gamma prev_gamma, pg_gamma out_gamma,
+                              const pg_samples *out, void *stream);
+
+/* Densities of given world directions (Eq. (2) under the same readings as
+ * pg_sample_mis): for n_per_px directions per pixel, dir [3][n*H*pitch],
+ * writes pdf_mix = D, and optionally pdf_guide = N(M^-1 w)/(2 pi) (the
+ * unweighted guided density) and pdf_brdf = p_b.  Zero for pixels with
+ * omega_o below the surface and for directions below the horizon. */
+pg_status pg_pdf(const pg_params *p, const pg_view *v, pg_gamma gamma, int32_t n_per_px,
+                 const float *dir, float *pdf_mix, float *pdf_guide, float *pdf_brdf,
+                 void *stream);
+
+/* Workload stand-in for the trace between sampling and training: writes
+ * samples->radiance for strategies 1 and 2 (0 otherwise) from the analytic
+ * light field; vis [H*pitch] holds bit l for light l.  `lights` is host
+ * memory read during the call. */
+pg_status pg_light_field(const pg_lights *lights, const pg_view *v, const uint8_t *vis,
+                         const pg_samples *samples, void *stream);
+
+/* Online weighted EM update of Gamma in place (Sec. 3.2, Sec. 4.2, Fig. 2).
+ * For each guided pixel: training set = own samples with strategy 1 in
+ * sample order, then N(k) = 5 + floor(15 (kMax - k)/kMax) picks with
+ * replacement among the samples of the (2R+1)^2 - 1 surrounding pixels
+ * (16-bit fields of Philox words, counter (y*width + x, frame,
+ * 2^16 + m/8, view)), kept if inside the image and of strategy 1.
+ * E-step per sample: u = M^-1(w), weight L f_r cos / p_b(source), posterior
+ * gamma of the Gaussian against the BRDF under the model's pi.  M-step:
+ * the batch mean/covariance merged with the state by eta = 1/(k+1) and the
+ * evidence W; pi = clamp(.., pi_lo, pi_hi) unless PG_NO_CLAMP; k += 1 (at
+ * most kMax).  An empty batch leaves the pixel unchanged.
+ * With PG_EM_BATCH in p->flags, `iterations` rounds of plain batch EM run on
+ * the same training set (mu, Sigma, pi replaced; W and k kept); otherwise
+ * `iterations` must be 1.  Reads samples->dir, pdf_brdf, strategy,
+ * radiance. */
+pg_status pg_em_update(const pg_params *p, const pg_view *v, const pg_samples *in,
+                       pg_gamma gamma_inout, int32_t iterations, void *stream);
+
+/* Radiance-weighted negative log-likelihood of the mixture over each pixel's
+ * EM training set and its adjoint.  theta [8][H*pitch] FP32 holds
+ * (mu_x, mu_y, l11, l21, l22, logit pi, unused, k) with Sigma = L L^T; the
+ * Gaussian uses Sigma + eps I.  Writes nll [H*pitch] (nullable) and, when
+ * grad_theta is not NULL, grad_theta = grad_out * dNLL/dtheta ([8][H*pitch];
+ * channels 6 and 7 are 0; grad_out NULL means 1). */
+pg_status pg_nll_backward(const pg_params *p, const pg_view *v, const pg_samples *in,
+                          const float *theta, const float *grad_out, float *grad_theta,
+                          float *nll, void *stream);
+
+/* Diagnostic: Philox4x32-10 (Salmon et al., SC 2011), the generator behind
+ * every random draw above, for n counters: counters [n][4] uint32 and out
+ * [n][4] uint32 are device arrays, key = (seed low word, seed high word). */
+pg_status pg_philox(int32_t n, const uint32_t *counters, uint64_t seed, uint32_t *out, void *stream);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char *pg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

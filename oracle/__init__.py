@@ -79,7 +79,7 @@ def _declare(L):
     L.orc_sample.argtypes = [P, P, P, i32, P, P, P, P, P, Rect]
     L.orc_pdf.argtypes = [P, P, P, i32, P, P, P, P, Rect]
     L.orc_light.argtypes = [i32, P, C.c_double, P, i32, i32, i32, i32, P, P, P, Rect]
-    L.orc_em.argtypes = [P, P, i32, P, P, P, P, P, i32, i32, Rect]
+    L.orc_em.argtypes = [P, P, i32, P, P, P, P, P, i32, i32, P, Rect]
     L.orc_nll.argtypes = [P, P, i32, P, P, P, P, P, P, P, P, Rect]
     L.orc_num_threads.restype = i32
 
@@ -283,16 +283,18 @@ def light(lights, ambient, vis, dirs, strategy, rect=None):
     return L
 
 
-def em(P, view, rec, gamma, iterations=1, batch=False, rect=None):
-    """Returns the updated state (the input array is not modified)."""
+def em(P, view, rec, gamma, iterations=1, batch=False, rect=None, with_stats=False):
+    """Returns the updated state (the input array is not modified), and with
+    with_stats the (B0, B1) evidences [2][H][W] of each pixel's last E-step."""
     g = _f64(gamma).copy()
     spp = rec["strategy"].shape[0]
     d, pb = _f64(rec["dir"]), _f64(rec["pdf_brdf"])
     st = np.ascontiguousarray(rec["strategy"], dtype=np.uint8)
     L = _f64(rec["radiance"])
+    stats = np.zeros((2,) + g.shape[1:]) if with_stats else None
     lib().orc_em(C.byref(P), C.byref(view.c), spp, _ptr(d), _ptr(pb), _ptr(st), _ptr(L), _ptr(g),
-                 iterations, int(bool(batch)), _rect(view, rect))
-    return g
+                 iterations, int(bool(batch)), _ptr(stats), _rect(view, rect))
+    return (g, stats) if with_stats else g
 
 
 def nll(P, view, rec, theta, grad_out=None, rect=None):
@@ -340,4 +342,5 @@ class Frames:
         g2 = em(P, v, rec, g1, rect=rect)
         self.gamma = g2
         self.view_prev = v
-        return dict(gamma_reproj=g1, src=src, rec=rec, gamma=g2)
+        self.last = dict(gamma_reproj=g1, src=src, rec=rec, gamma=g2)
+        return self.last

@@ -426,9 +426,14 @@ void orc_reproject(const orc_params *P, const orc_view *cur, const orc_view *pre
         float my = cur->motion ? cur->motion[pl + idx] : 0.0f;
         float fx = ((float)x + 0.5f) - mx;
         float fy = ((float)y + 0.5f) - my;
-        qx = (int)floorf(fx);
-        qy = (int)floorf(fy);
-        if (qx < 0 || qy < 0 || qx >= prev->width || qy >= prev->height) keep = 0;
+        /* floor(f) lies in [0, n) exactly when f does; the comparison also
+           sends a non-finite motion vector to a new model */
+        if (fx >= 0.0f && fy >= 0.0f && fx < (float)prev->width && fy < (float)prev->height) {
+          qx = (int)floorf(fx);
+          qy = (int)floorf(fy);
+        } else {
+          keep = 0;
+        }
       }
       int64_t qidx = 0;
       if (keep) {
@@ -596,7 +601,8 @@ void orc_pdf(const orc_params *P, const orc_view *v, const double *gamma, int32_
  * build has no geometry): a constant ambient term plus spherical-Gaussian
  * lights, each gated by a per-pixel visibility bit:
  *   L(p, w) = ambient + sum_l V(p, l) c_l exp(lambda_l (w.xi_l - 1)).
- * Null and missing samples carry no radiance. */
+ * with w and xi_l taken as unit vectors.  Null and missing samples carry no
+ * radiance. */
 void orc_light(int32_t n_lights, const float *lights, double ambient, const uint8_t *vis,
                int32_t width, int32_t height, int32_t pitch, int32_t spp, const double *dir,
                const uint8_t *strategy, double *radiance, orc_rect r) {
@@ -612,11 +618,13 @@ void orc_light(int32_t n_lights, const float *lights, double ambient, const uint
         double L = 0.0;
         if (strategy[o] == 1 || strategy[o] == 2) {
           double w[3] = {dir[o], dir[spl + o], dir[2 * spl + o]};
+          normalize3(w);
           L = ambient;
           for (int k = 0; k < n_lights; ++k) {
             if (!((vis[idx] >> k) & 1u)) continue;
             const float *lt = lights + 5 * k;
             double ax[3] = {lt[0], lt[1], lt[2]};
+            normalize3(ax);
             L += (double)lt[4] * exp((double)lt[3] * (dot3(w, ax) - 1.0));
           }
         }
@@ -812,7 +820,7 @@ static void gather_set(const orc_params *P, const orc_view *v, int32_t spp, cons
  * mu, Sigma and pi are replaced by the batch estimate; W and k are kept). */
 void orc_em(const orc_params *P, const orc_view *v, int32_t spp, const double *dir,
             const double *pdf_brdf, const uint8_t *strategy, const double *radiance,
-            double *gamma, int32_t iterations, int32_t batch, orc_rect r) {
+            double *gamma, int32_t iterations, int32_t batch, double *stats, orc_rect r) {
   const int H = v->height;
   const int64_t pl = (int64_t)H * v->pitch;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -821,6 +829,10 @@ void orc_em(const orc_params *P, const orc_view *v, int32_t spp, const double *d
     for (int x = r.x0; x < r.x1; ++x) {
       const int64_t idx = (int64_t)y * v->pitch + x;
       pixel_t px = load_pixel(P, v, idx);
+      if (stats) {
+        stats[idx] = 0.0;
+        stats[pl + idx] = 0.0;
+      }
       if (!px.guided) continue;
       double g[NCH];
       gamma_get(gamma, pl, idx, g);
@@ -837,6 +849,10 @@ void orc_em(const orc_params *P, const orc_view *v, int32_t spp, const double *d
         }
         double st[7];
         orc_batch_stats(n, &u[0][0], w, gam, st);
+        if (stats) {
+          stats[idx] = st[0];
+          stats[pl + idx] = st[1];
+        }
         if (!batch) {
           orc_merge(P, g, st, g);
         } else if (st[0] > 0.0) {

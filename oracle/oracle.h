@@ -107,9 +107,10 @@ void orc_light(int32_t n_lights, const float *lights /*[n][5] axis xyz, sharpnes
                double ambient, const uint8_t *vis, int32_t width, int32_t height,
                int32_t pitch, int32_t spp, const double *dir, const uint8_t *strategy,
                double *radiance, orc_rect r);
+/* stats (nullable) [2][H*pitch]: B0 and B1 of the pixel's last E-step. */
 void orc_em(const orc_params *P, const orc_view *v, int32_t spp, const double *dir,
             const double *pdf_brdf, const uint8_t *strategy, const double *radiance,
-            double *gamma, int32_t iterations, int32_t batch, orc_rect r);
+            double *gamma, int32_t iterations, int32_t batch, double *stats, orc_rect r);
 void orc_nll(const orc_params *P, const orc_view *v, int32_t spp, const double *dir,
              const double *pdf_brdf, const uint8_t *strategy, const double *radiance,
              const double *theta, const double *grad_out, double *grad, double *nll,

@@ -1,0 +1,275 @@
+// Device math for the path-guiding kernels (gfx950, FP32 arithmetic).
+//
+// Everything a kernel needs per pixel or per sample: the counter-based RNG,
+// the shading frame, the Shirley-Chiu map M and its inverse, the synthetic
+// Lambert + GGX material, the Gaussian on the unit square and the storage
+// conversions of the model planes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pgk {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kInvPi = 0.318309886183790671538f;
+constexpr float k4OverPi = 1.27323954473516268615f;
+constexpr float kInv4Pi2 = 0.0253302959105844428f;  // 1 / (4 pi^2)
+constexpr int kMaxSpp = 8;
+
+struct V3 {
+  float x, y, z;
+};
+
+__device__ __forceinline__ float dot3(V3 a, V3 b) { return fmaf(a.z, b.z, fmaf(a.y, b.y, a.x * b.x)); }
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC 2011): ten rounds, two 32x32 -> 64-bit
+// multiplications per round, key bumped by the Weyl constants.
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+// 24-bit uniform in [0, 1), exact in FP32.
+__device__ __forceinline__ float u24(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
+
+// ---------------------------------------------------------------------------
+// Shading frame: Duff et al., "Building an Orthonormal Basis, Revisited"
+// (JCGT 2017), around the normalised shading normal.
+struct Frame {
+  V3 t, b, n;
+};
+
+__device__ __forceinline__ Frame make_frame(V3 n) {
+  const float inv = __builtin_amdgcn_rsqf(dot3(n, n));
+  n = V3{n.x * inv, n.y * inv, n.z * inv};
+  const float sign = copysignf(1.0f, n.z);
+  const float a = -1.0f / (sign + n.z);
+  const float c = n.x * n.y * a;
+  Frame f;
+  f.t = V3{1.0f + sign * n.x * n.x * a, sign * c, -sign * n.x};
+  f.b = V3{c, sign + n.y * n.y * a, -n.y};
+  f.n = n;
+  return f;
+}
+__device__ __forceinline__ V3 to_local(const Frame &f, V3 w) { return V3{dot3(w, f.t), dot3(w, f.b), dot3(w, f.n)}; }
+__device__ __forceinline__ V3 to_world(const Frame &f, V3 l) {
+  return V3{fmaf(l.z, f.n.x, fmaf(l.y, f.b.x, l.x * f.t.x)),
+            fmaf(l.z, f.n.y, fmaf(l.y, f.b.y, l.x * f.t.y)),
+            fmaf(l.z, f.n.z, fmaf(l.y, f.b.z, l.x * f.t.z))};
+}
+__device__ __forceinline__ V3 normalized(V3 v) {
+  const float inv = __builtin_amdgcn_rsqf(dot3(v, v));
+  return V3{v.x * inv, v.y * inv, v.z * inv};
+}
+
+// ---------------------------------------------------------------------------
+// M: unit square -> upper hemisphere.  Concentric square-to-disk map of
+// Shirley and Chiu (JGT 1997) followed by the equal-area lift
+// (x, y) -> (x sqrt(2 - r^2), y sqrt(2 - r^2), 1 - r^2).  The sector angle is
+// kept in units of pi so that sincospi needs no multiplication by pi.
+__device__ __forceinline__ V3 sq2hemi(float ux, float uy) {
+  const float a = 2.0f * ux - 1.0f, b = 2.0f * uy - 1.0f;
+  float r, q;
+  if (fabsf(a) > fabsf(b)) {
+    r = a;
+    q = 0.25f * (b / a);
+  } else if (b != 0.0f) {
+    r = b;
+    q = 0.5f - 0.25f * (a / b);
+  } else {
+    return V3{0.0f, 0.0f, 1.0f};
+  }
+  float s, c;
+  sincospif(q, &s, &c);
+  const float r2 = r * r;
+  const float k = r * sqrtf(2.0f - r2);
+  return V3{k * c, k * s, 1.0f - r2};
+}
+
+// atan on [-1, 1]: odd polynomial t * P(t^2) of degree 17, coefficients
+// fitted for this library (max error 5.8e-9 in exact arithmetic, about
+// 1.4 ulp evaluated in FP32 by Horner's rule).
+__device__ __forceinline__ float atan_unit(float t) {
+  const float s = t * t;
+  float p = 2.456724411e-03f;
+  p = fmaf(p, s, -1.440135855e-02f);
+  p = fmaf(p, s, 3.978122771e-02f);
+  p = fmaf(p, s, -7.234857976e-02f);
+  p = fmaf(p, s, 1.049894691e-01f);
+  p = fmaf(p, s, -1.416122913e-01f);
+  p = fmaf(p, s, 1.998590678e-01f);
+  p = fmaf(p, s, -3.333259821e-01f);
+  p = fmaf(p, s, 9.999998808e-01f);
+  return t * p;
+}
+
+// M^-1 for a direction in the local frame with w.z >= 0 (|w| = 1 up to
+// rounding).  Squared disk radius (w_x^2 + w_y^2)/(1 + w_z) avoids the
+// cancellation of 1 - w_z; the disk angle inside each of the four concentric
+// sectors is atan of the ratio of the smaller to the larger of |w_x|, |w_y|
+// (the disk scaling cancels in that ratio).
+__device__ __forceinline__ void hemi2sq(V3 w, float &ux, float &uy) {
+  const float s2 = fmaf(w.x, w.x, w.y * w.y);
+  const float rho = sqrtf(s2 * __builtin_amdgcn_rcpf(1.0f + w.z));
+  const float ax = fabsf(w.x), ay = fabsf(w.y);
+  float a, b;
+  if (ax > ay) {
+    a = copysignf(rho, w.x);
+    b = a * k4OverPi * atan_unit(w.y * __builtin_amdgcn_rcpf(w.x));
+  } else if (ay > 0.0f) {
+    b = copysignf(rho, w.y);
+    a = b * k4OverPi * atan_unit(w.x * __builtin_amdgcn_rcpf(w.y));
+  } else {
+    a = 0.0f;
+    b = 0.0f;
+  }
+  ux = fmaf(0.5f, a, 0.5f);
+  uy = fmaf(0.5f, b, 0.5f);
+}
+
+// ---------------------------------------------------------------------------
+// Synthetic material: Lambert + GGX (Walter et al., EGSR 2007) with Smith G1
+// and Schlick F, alpha = roughness^2.  Sampling density
+// p_b = s_d wi_z/pi + (1 - s_d) D(h) h_z / (4 wo.h).
+struct Pixel {
+  Frame f;
+  V3 wo;        // local view direction
+  float alpha2;  // alpha^2
+  float albedo_pi;  // albedo / pi
+  float g1_wo_over_4wo;  // G1(wo) / (4 wo_z)
+  float f0, s_d;
+};
+
+__device__ __forceinline__ float smith_g1(V3 v, float alpha2) {
+  return 2.0f * v.z / (v.z + sqrtf(fmaf(alpha2, fmaf(v.x, v.x, v.y * v.y), v.z * v.z)));
+}
+
+// f_r and p_b of a local direction wi with wi.z > 0.  h is unnormalised:
+// D(h/|h|) = alpha^2 |h|^4 / (pi (h_x^2 + h_y^2 + alpha^2 h_z^2)^2).
+__device__ __forceinline__ void brdf_eval(const Pixel &px, V3 wi, float &f, float &pdf) {
+  const V3 h = V3{px.wo.x + wi.x, px.wo.y + wi.y, px.wo.z + wi.z};
+  const float hh = dot3(h, h);
+  const float den = fmaf(px.alpha2, h.z * h.z, fmaf(h.x, h.x, h.y * h.y));
+  const float rden = __builtin_amdgcn_rcpf(den);
+  const float D = px.alpha2 * kInvPi * (hh * rden) * (hh * rden);
+  const float woh_u = dot3(px.wo, h);  // |h| (wo . h_hat)
+  const float pggx = D * h.z * __builtin_amdgcn_rcpf(4.0f * woh_u);
+  pdf = fmaf(px.s_d * kInvPi, wi.z, (1.0f - px.s_d) * pggx);
+  const float woh = woh_u * __builtin_amdgcn_rsqf(hh);
+  const float m = 1.0f - woh;
+  const float m2 = m * m;
+  const float F = fmaf(1.0f - px.f0, m2 * m2 * m, px.f0);
+  const float g1wi = smith_g1(wi, px.alpha2);
+  f = fmaf(F * D * g1wi * px.g1_wo_over_4wo, __builtin_amdgcn_rcpf(wi.z), px.albedo_pi);
+}
+
+__device__ __forceinline__ float brdf_pdf_only(const Pixel &px, V3 wi) {
+  const V3 h = V3{px.wo.x + wi.x, px.wo.y + wi.y, px.wo.z + wi.z};
+  const float hh = dot3(h, h);
+  const float den = fmaf(px.alpha2, h.z * h.z, fmaf(h.x, h.x, h.y * h.y));
+  const float D = px.alpha2 * kInvPi * (hh / den) * (hh / den);
+  const float pggx = D * h.z / (4.0f * dot3(px.wo, h));
+  return fmaf(px.s_d * kInvPi, wi.z, (1.0f - px.s_d) * pggx);
+}
+
+// ---------------------------------------------------------------------------
+// Gaussian N(mu, Sigma + eps I) on the unit square via its lower Cholesky
+// factor; the Schur complement is floored at eps against rounding.
+struct Gauss {
+  float mx, my, l11, l21, l22, i11, i22, norm;  // norm = 1/(4 pi^2 l11 l22)
+};
+
+__device__ __forceinline__ Gauss gauss_setup(float mx, float my, float sxx, float sxy, float syy,
+                                             float eps) {
+  Gauss g;
+  g.mx = mx;
+  g.my = my;
+  g.l11 = sqrtf(fmaxf(sxx + eps, eps));
+  g.l21 = sxy / g.l11;
+  g.l22 = sqrtf(fmaxf((syy + eps) - g.l21 * g.l21, eps));
+  g.i11 = 1.0f / g.l11;
+  g.i22 = 1.0f / g.l22;
+  g.norm = kInv4Pi2 / (g.l11 * g.l22);
+  return g;
+}
+
+// Squared Mahalanobis distance |L^-1 (u - mu)|^2.
+__device__ __forceinline__ float gauss_q(const Gauss &g, float ux, float uy) {
+  const float z1 = (ux - g.mx) * g.i11;
+  const float z2 = (uy - g.my - g.l21 * z1) * g.i22;
+  return fmaf(z1, z1, z2 * z2);
+}
+
+// Solid-angle density N(u)/(2 pi), accurate exponential.
+__device__ __forceinline__ float gauss_pdf_acc(const Gauss &g, float ux, float uy) {
+  return g.norm * expf(-0.5f * gauss_q(g, ux, uy));
+}
+// Same with the hardware exp2 (about 1e-6 relative for the arguments met here).
+__device__ __forceinline__ float gauss_pdf_fast(const Gauss &g, float ux, float uy) {
+  return g.norm * __builtin_amdgcn_exp2f(-0.72134752044448170368f * gauss_q(g, ux, uy));
+}
+
+// ---------------------------------------------------------------------------
+// Storage of the model planes: FP32, FP16 or BF16, round-to-nearest-even.
+struct bf16s {
+  uint16_t bits;
+};
+
+template <typename T> struct GammaIO;
+template <> struct GammaIO<float> {
+  static __device__ __forceinline__ float load(const float *p) { return *p; }
+  static __device__ __forceinline__ void store(float *p, float v) { *p = v; }
+  static constexpr float kMax = 3.40282347e38f;
+};
+template <> struct GammaIO<_Float16> {
+  static __device__ __forceinline__ float load(const _Float16 *p) { return (float)*p; }
+  static __device__ __forceinline__ void store(_Float16 *p, float v) { *p = (_Float16)v; }
+  static constexpr float kMax = 65504.0f;
+};
+template <> struct GammaIO<bf16s> {
+  static __device__ __forceinline__ float load(const bf16s *p) {
+    return __uint_as_float(((uint32_t)p->bits) << 16);
+  }
+  static __device__ __forceinline__ void store(bf16s *p, float v) {
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) {
+      p->bits = (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+      return;
+    }
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    p->bits = (uint16_t)(u >> 16);
+  }
+  static constexpr float kMax = 3.38953139e38f;
+};
+
+template <typename T>
+__device__ __forceinline__ void gamma_load(const T *g, int plane, int idx, float out[8]) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c) out[c] = GammaIO<T>::load(g + c * plane + idx);
+}
+template <typename T>
+__device__ __forceinline__ void gamma_store(T *g, int plane, int idx, const float in[8]) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    float v = in[c];
+    if (c == 6) v = fminf(v, GammaIO<T>::kMax);
+    GammaIO<T>::store(g + c * plane + idx, v);
+  }
+}
+
+}  // namespace pgk

@@ -1,0 +1,654 @@
+// Kernels of the path-guiding hot path for gfx950.
+//
+// One lane per pixel.  Streaming passes (reprojection, sampling, densities,
+// light field) use 64x4 blocks so that each wave reads one 256-byte row
+// segment of every plane.  The training pass stages the sample records of a
+// tile plus a 3-pixel halo in LDS as float4 (direction, L/p_src or 0), so the
+// neighbour picks of Sec. 4.2 are LDS reads, and maps block ids to tiles so
+// that each XCD works on one contiguous band of the image (its L2 then holds
+// the halo rows its neighbours share).
+#pragma once
+#include "pg_device.hpp"
+
+namespace pgk {
+
+struct ViewK {
+  int W, H, pitch;
+  const float *n, *o, *z, *rough, *alb, *mv;
+  const uint8_t *mask;
+};
+
+struct ParamsK {
+  uint32_t key0, key1, frame, view;
+  int k_max;
+  float pi_init, pi_lo, pi_hi, eps, tau_z, tau_n, rough_min, s_d, f0;
+  uint32_t flags;
+};
+
+struct SamplesK {
+  int spp;
+  float *dir, *pmix, *pb, *L;
+  uint8_t *strat;
+};
+
+constexpr uint32_t kNoClamp = 1u;
+constexpr int kR = 3;                       // pick radius: 7x7 window
+constexpr int kSide = 2 * kR + 1;
+constexpr int kCand = kSide * kSide - 1;    // 48 neighbours
+
+__device__ __forceinline__ V3 load3(const float *p, int plane, int idx) {
+  return V3{p[idx], p[plane + idx], p[2 * plane + idx]};
+}
+
+__device__ __forceinline__ void gamma_reset(const ParamsK &P, float g[8]) {
+  g[0] = 0.5f;
+  g[1] = 0.5f;
+  g[2] = 1.0f / 12.0f;
+  g[3] = 0.0f;
+  g[4] = 1.0f / 12.0f;
+  g[5] = P.pi_init;
+  g[6] = 0.0f;
+  g[7] = 0.0f;
+}
+
+// Per-pixel material constants in the local frame.
+__device__ __forceinline__ Pixel make_pixel(const ParamsK &P, V3 n, V3 o, float rough, float albedo) {
+  Pixel px;
+  px.f = make_frame(n);
+  px.wo = to_local(px.f, normalized(o));
+  const float alpha = rough * rough;
+  px.alpha2 = alpha * alpha;
+  px.albedo_pi = albedo * kInvPi;
+  px.g1_wo_over_4wo = smith_g1(px.wo, px.alpha2) / (4.0f * px.wo.z);
+  px.f0 = P.f0;
+  px.s_d = P.s_d;
+  return px;
+}
+
+// ---------------------------------------------------------------------------
+// Reprojection of one pixel (Sec. 3.1).  The decisions that turn FP32 inputs
+// into a source address or a reset flag use explicit operation orders:
+// validity and the normal test are fma(z, z', fma(y, y', x * x')), the
+// address is (x + 1/2) - mv, the depth test |z - z'| > tau z.
+template <typename TG>
+__device__ __forceinline__ int reproject_pixel(const ParamsK &P, const ViewK &cur, const ViewK &prev,
+                                               const TG *__restrict__ gprev, bool has_prev, int x,
+                                               int y, float g[8]) {
+  const int plane = cur.H * cur.pitch;
+  const int idx = y * cur.pitch + x;
+  const V3 n = load3(cur.n, plane, idx);
+  const V3 o = load3(cur.o, plane, idx);
+  const bool guided = dot3(n, o) > 0.0f && cur.rough[idx] >= P.rough_min;
+  bool keep = has_prev && guided;
+  if (keep && cur.mask != nullptr && cur.mask[idx] != 0) keep = false;
+  int qx = 0, qy = 0;
+  if (keep) {
+    const float mx = cur.mv ? cur.mv[idx] : 0.0f;
+    const float my = cur.mv ? cur.mv[plane + idx] : 0.0f;
+    const float fx = ((float)x + 0.5f) - mx;
+    const float fy = ((float)y + 0.5f) - my;
+    if (fx >= 0.0f && fy >= 0.0f && fx < (float)prev.W && fy < (float)prev.H) {
+      qx = (int)floorf(fx);
+      qy = (int)floorf(fy);
+    } else {
+      keep = false;
+    }
+  }
+  if (keep) {
+    const int pplane = prev.H * prev.pitch;
+    const int qidx = qy * prev.pitch + qx;
+    const float zp = cur.z[idx], zq = prev.z[qidx];
+    if (fabsf(zp - zq) > P.tau_z * zp) keep = false;
+    const V3 nq = load3(prev.n, pplane, qidx);
+    if (dot3(n, nq) < P.tau_n) keep = false;
+    if (keep) {
+      gamma_load(gprev, pplane, qidx, g);
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (!isfinite(g[c])) keep = false;
+    }
+    if (keep && !(n.x == nq.x && n.y == nq.y && n.z == nq.z)) {
+      // change of hemisphere: keep the world direction of M(mu)
+      const Frame fq = make_frame(nq);
+      const Frame fp = make_frame(n);
+      const V3 lq = sq2hemi(fminf(fmaxf(g[0], 0.0f), 1.0f), fminf(fmaxf(g[1], 0.0f), 1.0f));
+      const V3 lp = to_local(fp, to_world(fq, lq));
+      if (lp.z <= 0.0f) {
+        keep = false;
+      } else {
+        hemi2sq(normalized(lp), g[0], g[1]);
+      }
+    }
+  }
+  if (!keep) {
+    gamma_reset(P, g);
+    return -1;
+  }
+  return qy * prev.W + qx;
+}
+
+// ---------------------------------------------------------------------------
+// Sampling of one pixel (Sec. 3.1, Eq. (2)).  Each strategy's own density is
+// taken in its sample space (Gaussian from z, GGX from xi_1), the other
+// component from the direction.
+__device__ __forceinline__ void sample_pixel(const ParamsK &P, const ViewK &v, const SamplesK &S,
+                                             int x, int y, const float g[8]) {
+  const int plane = v.H * v.pitch;
+  const int idx = y * v.pitch + x;
+  const int splane = S.spp * plane;
+  const V3 n = load3(v.n, plane, idx);
+  const V3 o = load3(v.o, plane, idx);
+  const float rough = v.rough[idx];
+  const bool valid = dot3(n, o) > 0.0f;
+  const bool guided = valid && rough >= P.rough_min;
+  const float pe = (guided && g[7] >= 1.0f) ? g[5] : 0.0f;
+  const Pixel px = make_pixel(P, n, o, rough, 0.0f);
+  const Gauss G = gauss_setup(g[0], g[1], g[2], g[3], g[4], P.eps);
+  const uint32_t pix = (uint32_t)(y * v.W + x);
+  for (int s = 0; s < S.spp; ++s) {
+    const int rec = (s * v.H + y) * v.pitch + x;
+    uint8_t code = 0;
+    V3 l = V3{0.0f, 0.0f, 0.0f};
+    float D = 0.0f, pb = 0.0f;
+    if (valid) {
+      const uint4 w4 = philox4x32_10(pix, P.frame, (uint32_t)s, P.view, P.key0, P.key1);
+      const float zeta = u24(w4.x), xl = u24(w4.y), x1 = u24(w4.z), x2 = u24(w4.w);
+      float sn, cs;
+      sincospif(2.0f * x2, &sn, &cs);
+      if (zeta < pe) {
+        const float rho = sqrtf(-2.0f * logf(1.0f - x1));
+        const float z1 = rho * cs, z2 = rho * sn;
+        const float ux = fmaf(G.l11, z1, G.mx);
+        const float uy = fmaf(G.l22, z2, fmaf(G.l21, z1, G.my));
+        if (ux >= 0.0f && ux <= 1.0f && uy >= 0.0f && uy <= 1.0f) {
+          l = sq2hemi(ux, uy);
+          const float pg = G.norm * expf(-0.5f * fmaf(z1, z1, z2 * z2));
+          pb = l.z > 0.0f ? brdf_pdf_only(px, l) : 0.0f;
+          D = fmaf(pe, pg, (1.0f - pe) * pb);
+          code = 2;
+        } else {
+          code = 3;
+        }
+      } else {
+        bool ok;
+        if (xl < P.s_d) {
+          const float r = sqrtf(x1);
+          l = V3{r * cs, r * sn, sqrtf(1.0f - x1)};
+          ok = l.z > 0.0f;
+          if (ok) pb = brdf_pdf_only(px, l);
+        } else {
+          const float t2 = px.alpha2 * x1 / (1.0f - x1);
+          const float ch = 1.0f / sqrtf(1.0f + t2);
+          const float sh = sqrtf(t2) * ch;
+          const V3 h = V3{sh * cs, sh * sn, ch};
+          const float woh = dot3(px.wo, h);
+          l = V3{2.0f * woh * h.x - px.wo.x, 2.0f * woh * h.y - px.wo.y, 2.0f * woh * h.z - px.wo.z};
+          ok = l.z > 0.0f && woh > 0.0f;
+          if (ok) {
+            // GGX density of the drawn normal in closed form of xi_1:
+            // D(h) = (1 - xi_1 (1 - alpha^2))^2 / (pi alpha^2)
+            const float q = fmaf(-x1, 1.0f - px.alpha2, 1.0f);
+            const float Dh = q * q / (kPi * px.alpha2);
+            const float pggx = Dh * ch / (4.0f * woh);
+            pb = fmaf(px.s_d * kInvPi, l.z, (1.0f - px.s_d) * pggx);
+          }
+        }
+        if (ok) {
+          float pg = 0.0f;
+          if (pe > 0.0f) {
+            float ux, uy;
+            hemi2sq(l, ux, uy);
+            pg = gauss_pdf_acc(G, ux, uy);
+          }
+          D = fmaf(pe, pg, (1.0f - pe) * pb);
+          code = 1;
+        } else {
+          code = 4;
+        }
+      }
+    }
+    V3 w = V3{0.0f, 0.0f, 0.0f};
+    if (code == 1 || code == 2) {
+      w = to_world(px.f, l);
+    } else {
+      D = 0.0f;
+      pb = 0.0f;
+    }
+    S.dir[rec] = w.x;
+    S.dir[splane + rec] = w.y;
+    S.dir[2 * splane + rec] = w.z;
+    S.pmix[rec] = D;
+    S.pb[rec] = pb;
+    S.strat[rec] = code;
+  }
+}
+
+template <typename TG>
+__global__ __launch_bounds__(256) void k_reproject(ParamsK P, ViewK cur, ViewK prev,
+                                                   const TG *__restrict__ gprev, TG *__restrict__ gout,
+                                                   int32_t *__restrict__ src_index, int has_prev) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  if (x >= cur.W || y >= cur.H) return;
+  float g[8];
+  const int src = reproject_pixel(P, cur, prev, gprev, has_prev != 0, x, y, g);
+  const int idx = y * cur.pitch + x;
+  gamma_store(gout, cur.H * cur.pitch, idx, g);
+  if (src_index) src_index[idx] = src;
+}
+
+template <typename TG>
+__global__ __launch_bounds__(256) void k_sample(ParamsK P, ViewK v, const TG *__restrict__ gamma,
+                                                SamplesK S) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  if (x >= v.W || y >= v.H) return;
+  float g[8];
+  gamma_load(gamma, v.H * v.pitch, y * v.pitch + x, g);
+  sample_pixel(P, v, S, x, y, g);
+}
+
+// Reprojection and sampling fused: the reprojected model stays in registers.
+// The sample pass sees the state exactly as stored (rounded to TG).
+template <typename TG>
+__global__ __launch_bounds__(256) void k_reproject_sample(ParamsK P, ViewK cur, ViewK prev,
+                                                          const TG *__restrict__ gprev,
+                                                          TG *__restrict__ gout, SamplesK S,
+                                                          int has_prev) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  if (x >= cur.W || y >= cur.H) return;
+  float g[8];
+  reproject_pixel(P, cur, prev, gprev, has_prev != 0, x, y, g);
+  const int idx = y * cur.pitch + x;
+  const int plane = cur.H * cur.pitch;
+  gamma_store(gout, plane, idx, g);
+  float gs[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    TG t;
+    GammaIO<TG>::store(&t, c == 6 ? fminf(g[c], GammaIO<TG>::kMax) : g[c]);
+    gs[c] = GammaIO<TG>::load(&t);
+  }
+  sample_pixel(P, cur, S, x, y, gs);
+}
+
+// Densities of given directions.
+template <typename TG>
+__global__ __launch_bounds__(256) void k_pdf(ParamsK P, ViewK v, const TG *__restrict__ gamma, int n_per_px,
+                                             const float *__restrict__ dir, float *__restrict__ pmix,
+                                             float *__restrict__ pguide, float *__restrict__ pbrdf) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  if (x >= v.W || y >= v.H) return;
+  const int plane = v.H * v.pitch;
+  const int idx = y * v.pitch + x;
+  const int dplane = n_per_px * plane;
+  float g[8];
+  gamma_load(gamma, plane, idx, g);
+  const V3 n = load3(v.n, plane, idx);
+  const V3 o = load3(v.o, plane, idx);
+  const float rough = v.rough[idx];
+  const bool valid = dot3(n, o) > 0.0f;
+  const bool guided = valid && rough >= P.rough_min;
+  const float pe = (guided && g[7] >= 1.0f) ? g[5] : 0.0f;
+  const Pixel px = make_pixel(P, n, o, rough, 0.0f);
+  const Gauss G = gauss_setup(g[0], g[1], g[2], g[3], g[4], P.eps);
+  for (int j = 0; j < n_per_px; ++j) {
+    const int r = (j * v.H + y) * v.pitch + x;
+    const V3 w = V3{dir[r], dir[dplane + r], dir[2 * dplane + r]};
+    float pg = 0.0f, pb = 0.0f;
+    const float ww = dot3(w, w);
+    if (valid && ww > 0.0f) {
+      const V3 l = to_local(px.f, normalized(w));
+      if (l.z > 0.0f) {
+        float ux, uy;
+        hemi2sq(l, ux, uy);
+        pg = gauss_pdf_acc(G, ux, uy);
+        pb = brdf_pdf_only(px, l);
+      }
+    }
+    pmix[r] = fmaf(pe, pg, (1.0f - pe) * pb);
+    if (pguide) pguide[r] = pg;
+    if (pbrdf) pbrdf[r] = pb;
+  }
+}
+
+// Analytic incident radiance (stand-in for the trace).  For unit w and xi,
+// w . xi - 1 = -|w - xi|^2 / 2, which has no cancellation near the axis.
+struct LightsK {
+  int count;
+  float ambient;
+  float l[8][5];
+};
+
+__global__ __launch_bounds__(256) void k_light(LightsK Lt, ViewK v, const uint8_t *__restrict__ vis,
+                                               SamplesK S) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  if (x >= v.W || y >= v.H) return;
+  const int plane = v.H * v.pitch;
+  const int idx = y * v.pitch + x;
+  const int splane = S.spp * plane;
+  const uint32_t bits = vis[idx];
+  for (int s = 0; s < S.spp; ++s) {
+    const int r = (s * v.H + y) * v.pitch + x;
+    const uint8_t code = S.strat[r];
+    float L = 0.0f;
+    if (code == 1 || code == 2) {
+      const V3 w = normalized(V3{S.dir[r], S.dir[splane + r], S.dir[2 * splane + r]});
+      L = Lt.ambient;
+      for (int k = 0; k < Lt.count; ++k) {
+        if (!((bits >> k) & 1u)) continue;
+        const V3 a = V3{w.x - Lt.l[k][0], w.y - Lt.l[k][1], w.z - Lt.l[k][2]};
+        L = fmaf(Lt.l[k][4], expf(-0.5f * Lt.l[k][3] * dot3(a, a)), L);
+      }
+    }
+    S.L[r] = L;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Training pass (Sec. 3.2, Sec. 4.2).
+//
+// Block = one TW x TH tile; LDS holds the records of the tile and a
+// 3-pixel halo for every sample index: float4 (direction, L / p_src) with 0
+// in the last slot for records that are not BRDF-strategy samples or lie
+// outside the image (such records add nothing to any sum, which is the same
+// as leaving them out of the training set).
+__device__ __forceinline__ int xcd_tile(int bid, int n) {
+  // blocks are dealt to the 8 XCDs round robin; give XCD j the j-th
+  // contiguous run of tiles
+  const int xcd = bid & 7, local = bid >> 3;
+  const int base = n >> 3, rem = n & 7;
+  return xcd * base + min(xcd, rem) + local;
+}
+
+template <int TW, int TH>
+__device__ __forceinline__ void stage_records(const ViewK &v, const SamplesK &S, float4 *lds, int tx0,
+                                              int ty0) {
+  constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH;
+  const int plane = v.H * v.pitch;
+  const int splane = S.spp * plane;
+  const int n = S.spp * SA;
+  for (int e = threadIdx.x; e < n; e += TW * TH) {
+    const int s = e / SA;
+    const int r = e - s * SA;
+    const int sy = r / SW, sx = r - sy * SW;
+    const int gx = tx0 - kR + sx, gy = ty0 - kR + sy;
+    float4 rec = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (gx >= 0 && gy >= 0 && gx < v.W && gy < v.H) {
+      const int o = (s * v.H + gy) * v.pitch + gx;
+      if (S.strat[o] == 1) {
+        const float p = S.pb[o];
+        if (p > 0.0f) rec = make_float4(S.dir[o], S.dir[splane + o], S.dir[2 * splane + o], S.L[o] / p);
+      }
+    }
+    lds[e] = rec;
+  }
+}
+
+// Running sums of one E-step: B0 = sum w, B1 = sum w gamma, and the
+// weighted mean (mx, my) and normalised scatter (sxx, sxy, syy) of u under the
+// weights v = w gamma, updated per sample in the pairwise form
+//   m += (v / B1') d,   S = (B1 / B1') (S + (v / B1') d d^T),   d = u - m,
+// which has no cancellation when a heavy sample follows light ones and needs
+// no reciprocal of a (possibly subnormal) evidence.
+struct Accum {
+  float B0, B1, mx, my, sxx, sxy, syy;
+};
+
+struct EmCtx {
+  Pixel px;
+  Gauss G;
+  float pi, one_m_pi;
+};
+
+__device__ __forceinline__ void em_visit(const EmCtx &c, float4 r, Accum &a) {
+  if (r.w == 0.0f) return;
+  const V3 l = to_local(c.px.f, V3{r.x, r.y, r.z});
+  if (l.z <= 0.0f) return;
+  float ux, uy, f, pb;
+  hemi2sq(l, ux, uy);
+  brdf_eval(c.px, l, f, pb);
+  const float w = r.w * f * l.z;
+  const float ga = c.pi * gauss_pdf_fast(c.G, ux, uy);
+  const float gb = c.one_m_pi * pb;
+  const float sum = ga + gb;
+  const float gam = sum > 0.0f ? ga / sum : 0.0f;
+  a.B0 += w;
+  const float vw = w * gam;
+  if (vw > 0.0f) {
+    const float bn = a.B1 + vw;
+    float fr, keep;
+    if (bn >= 1.17549435e-38f) {
+      const float rb = __builtin_amdgcn_rcpf(bn);
+      fr = vw * rb;
+      keep = a.B1 * rb;
+    } else {
+      fr = vw / bn;
+      keep = a.B1 / bn;
+    }
+    a.B1 = bn;
+    const float dx = ux - a.mx, dy = uy - a.my;
+    a.mx = fmaf(dx, fr, a.mx);
+    a.my = fmaf(dy, fr, a.my);
+    const float fx = fr * dx, fy = fr * dy;
+    a.sxx = keep * fmaf(fx, dx, a.sxx);
+    a.sxy = keep * fmaf(fx, dy, a.sxy);
+    a.syy = keep * fmaf(fy, dy, a.syy);
+  }
+}
+
+// Pick m of pixel (x, y): 16-bit field of a stream-1 Philox word -> (offset,
+// sample) uniform over the 48 neighbours times spp.  Returns the LDS index.
+template <int SW, int SA>
+__device__ __forceinline__ int pick_index(uint4 w4, int m, int spp, uint32_t cs, uint32_t inv_spp, int lx,
+                                          int ly) {
+  const int wsel = (m >> 1) & 3;
+  const uint32_t word = wsel == 0 ? w4.x : wsel == 1 ? w4.y : wsel == 2 ? w4.z : w4.w;
+  const uint32_t h = (m & 1) ? (word >> 16) : (word & 0xFFFFu);
+  const uint32_t c = (h * cs) >> 16;                  // [0, 48 spp)
+  const uint32_t o0 = (c * inv_spp) >> 16;            // c / spp (exact for c < 48 spp <= 384)
+  const int s = (int)(c - o0 * (uint32_t)spp);
+  const int o = (int)o0 + (o0 >= (uint32_t)(kCand / 2) ? 1 : 0);
+  const int dy = o / kSide - kR, dx = o - (o / kSide) * kSide - kR;
+  return s * SA + (ly + kR + dy) * SW + (lx + kR + dx);
+}
+
+template <typename TG, int TW, int TH>
+__global__ __launch_bounds__(TW *TH) void k_em(ParamsK P, ViewK v, SamplesK S, TG *__restrict__ gamma,
+                                               int iterations, int batch, int tiles_x, int n_tiles) {
+  extern __shared__ float4 lds[];
+  constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH;
+  const int tile = xcd_tile(blockIdx.x, n_tiles);
+  const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
+  stage_records<TW, TH>(v, S, lds, tx0, ty0);
+  __syncthreads();
+  const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+  const int x = tx0 + lx, y = ty0 + ly;
+  if (x >= v.W || y >= v.H) return;
+  const int plane = v.H * v.pitch;
+  const int idx = y * v.pitch + x;
+  const V3 n = load3(v.n, plane, idx);
+  const V3 o = load3(v.o, plane, idx);
+  const float rough = v.rough[idx];
+  if (!(dot3(n, o) > 0.0f && rough >= P.rough_min)) return;
+  float g[8];
+  gamma_load(gamma, plane, idx, g);
+  EmCtx c;
+  c.px = make_pixel(P, n, o, rough, v.alb[idx]);
+  int k = (int)g[7];
+  k = k < 0 ? 0 : (k > P.k_max ? P.k_max : k);
+  const int npick = 5 + (15 * (P.k_max - k)) / P.k_max;
+  const uint32_t pix = (uint32_t)(y * v.W + x);
+  const uint32_t cs = (uint32_t)(kCand * S.spp);
+  const uint32_t inv_spp = (65536u + (uint32_t)S.spp - 1u) / (uint32_t)S.spp;
+  const int own = (ly + kR) * SW + (lx + kR);
+  const int iters = batch ? iterations : 1;
+  for (int it = 0; it < iters; ++it) {
+    c.G = gauss_setup(g[0], g[1], g[2], g[3], g[4], P.eps);
+    c.pi = g[5];
+    c.one_m_pi = 1.0f - g[5];
+    Accum a = {0, 0, 0, 0, 0, 0, 0};
+    for (int s = 0; s < S.spp; ++s) em_visit(c, lds[s * SA + own], a);
+    uint4 w4 = make_uint4(0, 0, 0, 0);
+    for (int m = 0; m < npick; ++m) {
+      if ((m & 7) == 0) w4 = philox4x32_10(pix, P.frame, (1u << 16) | (uint32_t)(m >> 3), P.view, P.key0, P.key1);
+      em_visit(c, lds[pick_index<SW, SA>(w4, m, S.spp, cs, inv_spp, lx, ly)], a);
+    }
+    if (!(a.B0 > 0.0f)) break;
+    if (!batch) {
+      // stepwise merge with eta = 1/(k+1) and evidence W; only ratios of
+      // evidences appear, so a subnormal B1 is harmless
+      const float eta = 1.0f / (g[7] + 1.0f);
+      const float sw = fmaf(1.0f - eta, g[6], eta * a.B0);
+      const float so = (1.0f - eta) * g[5] * g[6];
+      const float sn = eta * a.B1;
+      const float sg = so + sn;
+      if (sg > 0.0f && a.B1 > 0.0f) {
+        const float al = so / sg, be = sn / sg;
+        const float dx = g[0] - a.mx, dy = g[1] - a.my;
+        const float ab = al * be;
+        g[0] = fmaf(al, g[0], be * a.mx);
+        g[1] = fmaf(al, g[1], be * a.my);
+        g[2] = fmaf(ab * dx, dx, fmaf(al, g[2], be * a.sxx));
+        g[3] = fmaf(ab * dx, dy, fmaf(al, g[3], be * a.sxy));
+        g[4] = fmaf(ab * dy, dy, fmaf(al, g[4], be * a.syy));
+      }
+      float pn = sg / sw;
+      if (!(P.flags & kNoClamp)) pn = fminf(fmaxf(pn, P.pi_lo), P.pi_hi);
+      g[5] = pn;
+      g[6] = sw;
+      g[7] = fminf(g[7] + 1.0f, (float)P.k_max);
+    } else {
+      if (a.B1 > 0.0f) {
+        g[0] = a.mx;
+        g[1] = a.my;
+        g[2] = a.sxx;
+        g[3] = a.sxy;
+        g[4] = a.syy;
+      }
+      float pn = a.B1 / a.B0;
+      if (!(P.flags & kNoClamp)) pn = fminf(fmaxf(pn, P.pi_lo), P.pi_hi);
+      g[5] = pn;
+    }
+  }
+  gamma_store(gamma, plane, idx, g);
+}
+
+// ---------------------------------------------------------------------------
+// Weighted NLL of the mixture over the training set and its adjoint.
+struct NllAccum {
+  float loss, gmx, gmy, gxx, gxy, gyy, gl;
+};
+
+struct NllCtx {
+  Pixel px;
+  Gauss G;
+  float pi, one_m_pi, mux, muy, ia, ib, ic;
+};
+
+__device__ __forceinline__ void nll_visit(const NllCtx &c, float4 r, NllAccum &a) {
+  if (r.w == 0.0f) return;
+  const V3 l = to_local(c.px.f, V3{r.x, r.y, r.z});
+  if (l.z <= 0.0f) return;
+  float ux, uy, f, pb;
+  hemi2sq(l, ux, uy);
+  brdf_eval(c.px, l, f, pb);
+  const float w = r.w * f * l.z;
+  const float pg = gauss_pdf_acc(c.G, ux, uy);
+  const float ga = c.pi * pg;
+  const float D = fmaf(c.one_m_pi, pb, ga);
+  a.loss = fmaf(-w, logf(D), a.loss);
+  const float gam = D > 0.0f ? ga / D : 0.0f;
+  const float dx = ux - c.mux, dy = uy - c.muy;
+  const float vx = fmaf(c.ia, dx, c.ib * dy), vy = fmaf(c.ib, dx, c.ic * dy);
+  const float wg = w * gam;
+  a.gmx = fmaf(-wg, vx, a.gmx);
+  a.gmy = fmaf(-wg, vy, a.gmy);
+  a.gxx = fmaf(-0.5f * wg, fmaf(vx, vx, -c.ia), a.gxx);
+  a.gxy = fmaf(-0.5f * wg, fmaf(vx, vy, -c.ib), a.gxy);
+  a.gyy = fmaf(-0.5f * wg, fmaf(vy, vy, -c.ic), a.gyy);
+  a.gl = fmaf(-w, gam - c.pi, a.gl);
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW *TH) void k_nll(ParamsK P, ViewK v, SamplesK S, const float *__restrict__ theta,
+                                                const float *__restrict__ grad_out, float *__restrict__ grad,
+                                                float *__restrict__ nll, int tiles_x, int n_tiles) {
+  extern __shared__ float4 lds[];
+  constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH;
+  const int tile = xcd_tile(blockIdx.x, n_tiles);
+  const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
+  stage_records<TW, TH>(v, S, lds, tx0, ty0);
+  __syncthreads();
+  const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+  const int x = tx0 + lx, y = ty0 + ly;
+  if (x >= v.W || y >= v.H) return;
+  const int plane = v.H * v.pitch;
+  const int idx = y * v.pitch + x;
+  const V3 n = load3(v.n, plane, idx);
+  const V3 o = load3(v.o, plane, idx);
+  const float rough = v.rough[idx];
+  float th[8];
+#pragma unroll
+  for (int ch = 0; ch < 8; ++ch) th[ch] = theta[ch * plane + idx];
+  NllAccum a = {0, 0, 0, 0, 0, 0, 0};
+  float gr[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (dot3(n, o) > 0.0f && rough >= P.rough_min) {
+    NllCtx c;
+    c.px = make_pixel(P, n, o, rough, v.alb[idx]);
+    const float l11 = th[2], l21 = th[3], l22 = th[4];
+    const float sxx = l11 * l11, sxy = l11 * l21, syy = fmaf(l21, l21, l22 * l22);
+    c.G = gauss_setup(th[0], th[1], sxx, sxy, syy, P.eps);
+    c.pi = 1.0f / (1.0f + expf(-th[5]));
+    c.one_m_pi = 1.0f - c.pi;
+    c.mux = th[0];
+    c.muy = th[1];
+    const float A = sxx + P.eps, B = sxy, Cc = syy + P.eps;
+    const float idet = 1.0f / fmaf(A, Cc, -B * B);
+    c.ia = Cc * idet;
+    c.ib = -B * idet;
+    c.ic = A * idet;
+    int k = (int)th[7];
+    k = k < 0 ? 0 : (k > P.k_max ? P.k_max : k);
+    const int npick = 5 + (15 * (P.k_max - k)) / P.k_max;
+    const uint32_t pix = (uint32_t)(y * v.W + x);
+    const uint32_t cs = (uint32_t)(kCand * S.spp);
+    const uint32_t inv_spp = (65536u + (uint32_t)S.spp - 1u) / (uint32_t)S.spp;
+    const int own = (ly + kR) * SW + (lx + kR);
+    for (int s = 0; s < S.spp; ++s) nll_visit(c, lds[s * SA + own], a);
+    uint4 w4 = make_uint4(0, 0, 0, 0);
+    for (int m = 0; m < npick; ++m) {
+      if ((m & 7) == 0) w4 = philox4x32_10(pix, P.frame, (1u << 16) | (uint32_t)(m >> 3), P.view, P.key0, P.key1);
+      nll_visit(c, lds[pick_index<SW, SA>(w4, m, S.spp, cs, inv_spp, lx, ly)], a);
+    }
+    const float sc = grad_out ? grad_out[idx] : 1.0f;
+    gr[0] = sc * a.gmx;
+    gr[1] = sc * a.gmy;
+    gr[2] = sc * 2.0f * fmaf(a.gxx, l11, a.gxy * l21);
+    gr[3] = sc * 2.0f * fmaf(a.gxy, l11, a.gyy * l21);
+    gr[4] = sc * 2.0f * (a.gyy * l22);
+    gr[5] = sc * a.gl;
+  }
+  if (grad) {
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) grad[ch * plane + idx] = gr[ch];
+  }
+  if (nll) nll[idx] = a.loss;
+}
+
+// Philox words for given counters (diagnostic entry).
+__global__ void k_philox(int n, const uint32_t *__restrict__ ctr, uint32_t key0, uint32_t key1,
+                         uint32_t *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint4 r = philox4x32_10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], key0, key1);
+  out[4 * i] = r.x;
+  out[4 * i + 1] = r.y;
+  out[4 * i + 2] = r.z;
+  out[4 * i + 3] = r.w;
+}
+
+}  // namespace pgk

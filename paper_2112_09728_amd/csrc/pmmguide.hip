@@ -1,0 +1,383 @@
+// C ABI of libpmmguide: argument checks on the host, then kernel launches
+// on the caller's stream.  The operations are specified in pmmguide.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+
+#include "pg_kernels.hpp"
+#include "pmmguide.h"
+
+using namespace pgk;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pg_status fail(pg_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+pg_status fail(pg_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+pg_status ok() {
+  g_last_error.clear();
+  return PG_OK;
+}
+
+pg_status check_launch(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(PG_ERR_HIP, "%s: launch failed: %s", what, hipGetErrorString(e));
+  return ok();
+}
+
+constexpr int kMaxDim = 16384;
+
+pg_status check_params(const pg_params *p) {
+  if (!p) return fail(PG_ERR_ARG, "params is NULL");
+  if (p->k_max < 1 || p->k_max > 1000000) return fail(PG_ERR_ARG, "k_max must be >= 1");
+  if (p->radius != kR) return fail(PG_ERR_UNSUPPORTED, "radius %d: only %d is built", p->radius, kR);
+  if (!(p->eps_sigma > 0.0f) && p->eps_sigma != 0.0f) return fail(PG_ERR_ARG, "eps_sigma must be >= 0");
+  if (!(p->pi_lo <= p->pi_hi)) return fail(PG_ERR_ARG, "pi_lo > pi_hi");
+  if (!(p->s_diffuse >= 0.0f && p->s_diffuse <= 1.0f)) return fail(PG_ERR_ARG, "s_diffuse outside [0, 1]");
+  return PG_OK;
+}
+
+pg_status check_view(const pg_view *v, const char *name, bool need_albedo) {
+  if (!v) return fail(PG_ERR_ARG, "%s is NULL", name);
+  if (v->width <= 0 || v->height <= 0) return fail(PG_ERR_ARG, "%s: width/height must be > 0", name);
+  if (v->pitch < v->width) return fail(PG_ERR_ARG, "%s: pitch %d < width %d", name, v->pitch, v->width);
+  if (v->width > kMaxDim || v->height > kMaxDim)
+    return fail(PG_ERR_UNSUPPORTED, "%s: %dx%d exceeds %d", name, v->width, v->height, kMaxDim);
+  if ((int64_t)v->pitch * v->height * 8 * 3 >= ((int64_t)1 << 31))
+    return fail(PG_ERR_UNSUPPORTED, "%s: pitch*height too large for 32-bit indexing", name);
+  if (!v->normal || !v->view_dir || !v->depth || !v->roughness)
+    return fail(PG_ERR_ARG, "%s: normal, view_dir, depth and roughness are required", name);
+  if (need_albedo && !v->albedo) return fail(PG_ERR_ARG, "%s: albedo is required", name);
+  return PG_OK;
+}
+
+pg_status check_gamma(pg_gamma g, const char *name) {
+  if (!g.data) return fail(PG_ERR_ARG, "%s.data is NULL", name);
+  if (g.dtype != PG_F32 && g.dtype != PG_F16 && g.dtype != PG_BF16)
+    return fail(PG_ERR_ARG, "%s: unknown dtype %d", name, g.dtype);
+  return PG_OK;
+}
+
+pg_status check_samples(const pg_samples *s, bool need_pdfmix, bool need_radiance) {
+  if (!s) return fail(PG_ERR_ARG, "samples is NULL");
+  if (s->spp < 1 || s->spp > kMaxSpp) return fail(PG_ERR_ARG, "spp %d outside [1, %d]", s->spp, kMaxSpp);
+  if (!s->dir || !s->pdf_brdf || !s->strategy) return fail(PG_ERR_ARG, "samples: dir, pdf_brdf, strategy required");
+  if (need_pdfmix && !s->pdf_mix) return fail(PG_ERR_ARG, "samples: pdf_mix required");
+  if (need_radiance && !s->radiance) return fail(PG_ERR_ARG, "samples: radiance required");
+  return PG_OK;
+}
+
+ParamsK to_k(const pg_params *p) {
+  ParamsK k;
+  k.key0 = (uint32_t)(p->seed & 0xFFFFFFFFull);
+  k.key1 = (uint32_t)(p->seed >> 32);
+  k.frame = p->frame;
+  k.view = p->view;
+  k.k_max = p->k_max;
+  k.pi_init = p->pi_init;
+  k.pi_lo = p->pi_lo;
+  k.pi_hi = p->pi_hi;
+  k.eps = p->eps_sigma;
+  k.tau_z = p->tau_depth;
+  k.tau_n = p->tau_normal;
+  k.rough_min = p->rough_min;
+  k.s_d = p->s_diffuse;
+  k.f0 = p->f0;
+  k.flags = p->flags;
+  return k;
+}
+
+ViewK to_k(const pg_view *v) {
+  ViewK k;
+  k.W = v->width;
+  k.H = v->height;
+  k.pitch = v->pitch;
+  k.n = v->normal;
+  k.o = v->view_dir;
+  k.z = v->depth;
+  k.rough = v->roughness;
+  k.alb = v->albedo;
+  k.mv = v->motion;
+  k.mask = v->disocc;
+  return k;
+}
+
+SamplesK to_k(const pg_samples *s) {
+  SamplesK k;
+  k.spp = s->spp;
+  k.dir = s->dir;
+  k.pmix = s->pdf_mix;
+  k.pb = s->pdf_brdf;
+  k.L = s->radiance;
+  k.strat = s->strategy;
+  return k;
+}
+
+dim3 stream_grid(int W, int H) { return dim3((W + 63) / 64, (H + 3) / 4); }
+
+template <typename F>
+pg_status dispatch_dtype(int dtype, F &&f) {
+  switch (dtype) {
+    case PG_F32: return f((float *)nullptr);
+    case PG_F16: return f((_Float16 *)nullptr);
+    case PG_BF16: return f((bf16s *)nullptr);
+  }
+  return fail(PG_ERR_ARG, "unknown dtype %d", dtype);
+}
+
+// Training tile shapes built into the library.
+struct Tile {
+  int w, h;
+};
+constexpr Tile kTiles[] = {{32, 8}, {16, 16}, {64, 4}, {32, 4}, {16, 8}, {64, 2}};
+
+Tile default_tile(int spp) { return spp <= 4 ? Tile{32, 8} : Tile{32, 4}; }
+
+size_t tile_lds(Tile t, int spp) { return (size_t)(t.w + 2 * kR) * (t.h + 2 * kR) * spp * sizeof(float4); }
+
+pg_status pick_tile(const pg_params *p, int spp, Tile &t) {
+  if (p->tile_w == 0 && p->tile_h == 0) {
+    t = default_tile(spp);
+  } else {
+    bool found = false;
+    for (const Tile &c : kTiles)
+      if (c.w == p->tile_w && c.h == p->tile_h) found = true;
+    if (!found) return fail(PG_ERR_UNSUPPORTED, "tile %dx%d is not built", p->tile_w, p->tile_h);
+    t = Tile{p->tile_w, p->tile_h};
+  }
+  if (tile_lds(t, spp) > 64 * 1024)
+    return fail(PG_ERR_UNSUPPORTED, "tile %dx%d with spp %d needs %zu B of LDS (> 64 KiB)", t.w, t.h, spp,
+                tile_lds(t, spp));
+  return PG_OK;
+}
+
+template <typename TG, int TW, int TH>
+void launch_em_t(const ParamsK &P, const ViewK &v, const SamplesK &S, TG *g, int iters, int batch,
+                 hipStream_t st) {
+  const int tx = (v.W + TW - 1) / TW, ty = (v.H + TH - 1) / TH;
+  const int n = tx * ty;
+  const size_t lds = (size_t)(TW + 2 * kR) * (TH + 2 * kR) * S.spp * sizeof(float4);
+  hipLaunchKernelGGL((k_em<TG, TW, TH>), dim3(n), dim3(TW * TH), lds, st, P, v, S, g, iters, batch, tx, n);
+}
+
+template <typename TG>
+void launch_em(Tile t, const ParamsK &P, const ViewK &v, const SamplesK &S, TG *g, int iters, int batch,
+               hipStream_t st) {
+  if (t.w == 32 && t.h == 8) launch_em_t<TG, 32, 8>(P, v, S, g, iters, batch, st);
+  else if (t.w == 16 && t.h == 16) launch_em_t<TG, 16, 16>(P, v, S, g, iters, batch, st);
+  else if (t.w == 64 && t.h == 4) launch_em_t<TG, 64, 4>(P, v, S, g, iters, batch, st);
+  else if (t.w == 32 && t.h == 4) launch_em_t<TG, 32, 4>(P, v, S, g, iters, batch, st);
+  else if (t.w == 16 && t.h == 8) launch_em_t<TG, 16, 8>(P, v, S, g, iters, batch, st);
+  else launch_em_t<TG, 64, 2>(P, v, S, g, iters, batch, st);
+}
+
+template <int TW, int TH>
+void launch_nll_t(const ParamsK &P, const ViewK &v, const SamplesK &S, const float *theta, const float *go,
+                  float *grad, float *nll, hipStream_t st) {
+  const int tx = (v.W + TW - 1) / TW, ty = (v.H + TH - 1) / TH;
+  const int n = tx * ty;
+  const size_t lds = (size_t)(TW + 2 * kR) * (TH + 2 * kR) * S.spp * sizeof(float4);
+  hipLaunchKernelGGL((k_nll<TW, TH>), dim3(n), dim3(TW * TH), lds, st, P, v, S, theta, go, grad, nll, tx, n);
+}
+
+void launch_nll(Tile t, const ParamsK &P, const ViewK &v, const SamplesK &S, const float *theta,
+                const float *go, float *grad, float *nll, hipStream_t st) {
+  if (t.w == 32 && t.h == 8) launch_nll_t<32, 8>(P, v, S, theta, go, grad, nll, st);
+  else if (t.w == 16 && t.h == 16) launch_nll_t<16, 16>(P, v, S, theta, go, grad, nll, st);
+  else if (t.w == 64 && t.h == 4) launch_nll_t<64, 4>(P, v, S, theta, go, grad, nll, st);
+  else if (t.w == 32 && t.h == 4) launch_nll_t<32, 4>(P, v, S, theta, go, grad, nll, st);
+  else if (t.w == 16 && t.h == 8) launch_nll_t<16, 8>(P, v, S, theta, go, grad, nll, st);
+  else launch_nll_t<64, 2>(P, v, S, theta, go, grad, nll, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+pg_status pg_params_default(pg_params *p) {
+  if (!p) return fail(PG_ERR_ARG, "params is NULL");
+  std::memset(p, 0, sizeof(*p));
+  p->k_max = 16;
+  p->radius = 3;
+  p->pi_init = 0.05f;
+  p->pi_lo = 0.05f;
+  p->pi_hi = 0.95f;
+  p->eps_sigma = 2.5e-4f;
+  p->tau_depth = 0.1f;
+  p->tau_normal = 0.9f;
+  p->rough_min = 0.1f;
+  p->s_diffuse = 0.5f;
+  p->f0 = 0.04f;
+  return ok();
+}
+
+pg_status pg_reproject(const pg_params *p, const pg_view *cur, const pg_view *prev, pg_gamma prev_gamma,
+                       pg_gamma out_gamma, int32_t *src_index, void *stream) {
+  pg_status st;
+  if ((st = check_params(p)) || (st = check_view(cur, "cur", false)) || (st = check_gamma(out_gamma, "out_gamma")))
+    return st;
+  const bool has_prev = p->frame > 0;
+  if (has_prev) {
+    if ((st = check_view(prev, "prev", false)) || (st = check_gamma(prev_gamma, "prev_gamma"))) return st;
+    if (prev_gamma.dtype != out_gamma.dtype) return fail(PG_ERR_ARG, "prev_gamma and out_gamma dtypes differ");
+    if (prev_gamma.data == out_gamma.data) return fail(PG_ERR_ARG, "prev_gamma aliases out_gamma");
+  }
+  const ParamsK P = to_k(p);
+  const ViewK C = to_k(cur);
+  const ViewK Q = has_prev ? to_k(prev) : C;
+  hipStream_t s = (hipStream_t)stream;
+  return dispatch_dtype(out_gamma.dtype, [&](auto *tag) {
+    using TG = std::remove_pointer_t<decltype(tag)>;
+    hipLaunchKernelGGL((k_reproject<TG>), stream_grid(C.W, C.H), dim3(64, 4), 0, s, P, C, Q,
+                       (const TG *)(has_prev ? prev_gamma.data : out_gamma.data), (TG *)out_gamma.data,
+                       src_index, has_prev ? 1 : 0);
+    return check_launch("pg_reproject");
+  });
+}
+
+pg_status pg_sample_mis(const pg_params *p, const pg_view *v, pg_gamma gamma, const pg_samples *out,
+                        void *stream) {
+  pg_status st;
+  if ((st = check_params(p)) || (st = check_view(v, "view", false)) || (st = check_gamma(gamma, "gamma")) ||
+      (st = check_samples(out, true, false)))
+    return st;
+  const ParamsK P = to_k(p);
+  const ViewK V = to_k(v);
+  const SamplesK S = to_k(out);
+  hipStream_t s = (hipStream_t)stream;
+  return dispatch_dtype(gamma.dtype, [&](auto *tag) {
+    using TG = std::remove_pointer_t<decltype(tag)>;
+    hipLaunchKernelGGL((k_sample<TG>), stream_grid(V.W, V.H), dim3(64, 4), 0, s, P, V, (const TG *)gamma.data, S);
+    return check_launch("pg_sample_mis");
+  });
+}
+
+pg_status pg_reproject_sample(const pg_params *p, const pg_view *cur, const pg_view *prev, pg_gamma prev_gamma,
+                              pg_gamma out_gamma, const pg_samples *out, void *stream) {
+  pg_status st;
+  if ((st = check_params(p)) || (st = check_view(cur, "cur", false)) ||
+      (st = check_gamma(out_gamma, "out_gamma")) || (st = check_samples(out, true, false)))
+    return st;
+  const bool has_prev = p->frame > 0;
+  if (has_prev) {
+    if ((st = check_view(prev, "prev", false)) || (st = check_gamma(prev_gamma, "prev_gamma"))) return st;
+    if (prev_gamma.dtype != out_gamma.dtype) return fail(PG_ERR_ARG, "prev_gamma and out_gamma dtypes differ");
+    if (prev_gamma.data == out_gamma.data) return fail(PG_ERR_ARG, "prev_gamma aliases out_gamma");
+  }
+  const ParamsK P = to_k(p);
+  const ViewK C = to_k(cur);
+  const ViewK Q = has_prev ? to_k(prev) : C;
+  const SamplesK S = to_k(out);
+  hipStream_t s = (hipStream_t)stream;
+  return dispatch_dtype(out_gamma.dtype, [&](auto *tag) {
+    using TG = std::remove_pointer_t<decltype(tag)>;
+    hipLaunchKernelGGL((k_reproject_sample<TG>), stream_grid(C.W, C.H), dim3(64, 4), 0, s, P, C, Q,
+                       (const TG *)(has_prev ? prev_gamma.data : out_gamma.data), (TG *)out_gamma.data, S,
+                       has_prev ? 1 : 0);
+    return check_launch("pg_reproject_sample");
+  });
+}
+
+pg_status pg_pdf(const pg_params *p, const pg_view *v, pg_gamma gamma, int32_t n_per_px, const float *dir,
+                 float *pdf_mix, float *pdf_guide, float *pdf_brdf, void *stream) {
+  pg_status st;
+  if ((st = check_params(p)) || (st = check_view(v, "view", false)) || (st = check_gamma(gamma, "gamma")))
+    return st;
+  if (n_per_px < 1 || n_per_px > 64) return fail(PG_ERR_ARG, "n_per_px %d outside [1, 64]", n_per_px);
+  if ((int64_t)v->pitch * v->height * n_per_px * 3 >= ((int64_t)1 << 31))
+    return fail(PG_ERR_UNSUPPORTED, "n_per_px * pitch * height too large for 32-bit indexing");
+  if (!dir || !pdf_mix) return fail(PG_ERR_ARG, "dir and pdf_mix are required");
+  const ParamsK P = to_k(p);
+  const ViewK V = to_k(v);
+  hipStream_t s = (hipStream_t)stream;
+  return dispatch_dtype(gamma.dtype, [&](auto *tag) {
+    using TG = std::remove_pointer_t<decltype(tag)>;
+    hipLaunchKernelGGL((k_pdf<TG>), stream_grid(V.W, V.H), dim3(64, 4), 0, s, P, V, (const TG *)gamma.data,
+                       n_per_px, dir, pdf_mix, pdf_guide, pdf_brdf);
+    return check_launch("pg_pdf");
+  });
+}
+
+pg_status pg_light_field(const pg_lights *lights, const pg_view *v, const uint8_t *vis, const pg_samples *samples,
+                         void *stream) {
+  pg_status st;
+  if (!lights) return fail(PG_ERR_ARG, "lights is NULL");
+  if (lights->count < 0 || lights->count > PG_MAX_LIGHTS) return fail(PG_ERR_ARG, "lights->count out of range");
+  if ((st = check_view(v, "view", false)) || (st = check_samples(samples, false, true))) return st;
+  if (!vis && lights->count > 0) return fail(PG_ERR_ARG, "vis is NULL");
+  LightsK L;
+  std::memset(&L, 0, sizeof(L));
+  L.count = lights->count;
+  L.ambient = lights->ambient;
+  for (int k = 0; k < lights->count; ++k)
+    for (int c = 0; c < 5; ++c) L.l[k][c] = lights->light[k][c];
+  const ViewK V = to_k(v);
+  const SamplesK S = to_k(samples);
+  hipLaunchKernelGGL(k_light, stream_grid(V.W, V.H), dim3(64, 4), 0, (hipStream_t)stream, L, V, vis, S);
+  return check_launch("pg_light_field");
+}
+
+pg_status pg_em_update(const pg_params *p, const pg_view *v, const pg_samples *in, pg_gamma gamma_inout,
+                       int32_t iterations, void *stream) {
+  pg_status st;
+  if ((st = check_params(p)) || (st = check_view(v, "view", true)) || (st = check_gamma(gamma_inout, "gamma")) ||
+      (st = check_samples(in, false, true)))
+    return st;
+  const int batch = (p->flags & PG_EM_BATCH) ? 1 : 0;
+  if (iterations < 1 || (!batch && iterations != 1) || iterations > 1000)
+    return fail(PG_ERR_ARG, "iterations %d invalid (1 without PG_EM_BATCH, 1..1000 with it)", iterations);
+  Tile t;
+  if ((st = pick_tile(p, in->spp, t))) return st;
+  const ParamsK P = to_k(p);
+  const ViewK V = to_k(v);
+  const SamplesK S = to_k(in);
+  hipStream_t s = (hipStream_t)stream;
+  return dispatch_dtype(gamma_inout.dtype, [&](auto *tag) {
+    using TG = std::remove_pointer_t<decltype(tag)>;
+    launch_em<TG>(t, P, V, S, (TG *)gamma_inout.data, iterations, batch, s);
+    return check_launch("pg_em_update");
+  });
+}
+
+pg_status pg_nll_backward(const pg_params *p, const pg_view *v, const pg_samples *in, const float *theta,
+                          const float *grad_out, float *grad_theta, float *nll, void *stream) {
+  pg_status st;
+  if ((st = check_params(p)) || (st = check_view(v, "view", true)) || (st = check_samples(in, false, true)))
+    return st;
+  if (!theta) return fail(PG_ERR_ARG, "theta is NULL");
+  if (!grad_theta && !nll) return fail(PG_ERR_ARG, "nothing to compute: grad_theta and nll are NULL");
+  Tile t;
+  if ((st = pick_tile(p, in->spp, t))) return st;
+  const ParamsK P = to_k(p);
+  const ViewK V = to_k(v);
+  const SamplesK S = to_k(in);
+  launch_nll(t, P, V, S, theta, grad_out, grad_theta, nll, (hipStream_t)stream);
+  return check_launch("pg_nll_backward");
+}
+
+/* Diagnostic: Philox4x32-10 words for n counters (device arrays [n][4]). */
+pg_status pg_philox(int32_t n, const uint32_t *counters, uint64_t seed, uint32_t *out, void *stream) {
+  if (n < 0 || (n > 0 && (!counters || !out))) return fail(PG_ERR_ARG, "pg_philox: bad arguments");
+  if (n == 0) return ok();
+  hipLaunchKernelGGL(k_philox, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, n, counters,
+                     (uint32_t)(seed & 0xFFFFFFFFull), (uint32_t)(seed >> 32), out);
+  return check_launch("pg_philox");
+}
+
+const char *pg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
