@@ -1,7 +1,7 @@
 """Benchmark of the path-guiding hot path on one MI355X.
 
-One step = one frame of the 1920x1080, 1 spp, 64-frame workload with moving
-camera (motion U[-2,2] px, 2% disocclusion): reprojection + guided sampling
+One step = one frame of the 1920x1080, 1 spp, 64-frame camera-pan workload
+(pan steps U[-2,2]^2 px, 2% disocclusion): reprojection + guided sampling
 (one fused launch), the analytic light field standing in for the trace (timed
 on its own, excluded from the metric), and the online EM update.  Frames
 0..warmup-1 run untimed, frames warmup..warmup+steps-1 are timed; the default
@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0,
                     help="budget of the oracle timing on the host (0 = skip)")
     ap.add_argument("--seed", type=int, default=None)
+    ap.add_argument("--tile", default=None, help="training tile WxH (default: the library's)")
     return ap.parse_args()
 
 
@@ -81,22 +82,26 @@ def main():
     G = 32 if a.gamma_dtype == "f32" else 16
     frames = a.warmup + a.steps
     t0 = time.time()
-    scene = wl.make_scene(W, H, seed)
-    mvs, masks = [], []
+    seq = wl.Sequence(W, H, seed, moving=True)
+    dev_frames = []
     for t in range(frames):
-        mv, m = wl.make_motion(W, H, seed, t, moving=True)
-        mvs.append(torch.as_tensor(mv).cuda())
-        masks.append(torch.as_tensor(m).cuda())
-    guide = pg.Guide(scene, spp=S, seed=seed, gamma_dtype=dt, fused=not a.unfused)
-    views = [guide.view_for(mvs[t], masks[t]) for t in range(frames)]
+        fr = seq.frame(t)
+        dev_frames.append(pg.DeviceFrame(fr))
+        if t == 0:
+            lights, ambient = fr["lights"], fr["ambient"]
+    over = {}
+    if a.tile:
+        over["tile_w"], over["tile_h"] = (int(v) for v in a.tile.lower().split("x"))
+    guide = pg.Guide(W, H, lights, ambient, spp=S, seed=seed, gamma_dtype=dt, fused=not a.unfused,
+                     **over)
     torch.cuda.synchronize()
     print(f"bench: setup {time.time() - t0:.1f} s ({W}x{H}, spp {S}, Gamma {a.gamma_dtype}, "
-          f"{frames} frames)", file=sys.stderr, flush=True)
+          f"{frames} frames resident on the device)", file=sys.stderr, flush=True)
 
     def frame(t, ev=None):
         p = guide.params(t)
-        cur = views[t]
-        prev = guide.prev_base if t > 0 else None
+        cur = dev_frames[t].view
+        prev = dev_frames[t - 1].view if t > 0 else None
         g_prev, g_out = guide.gamma[guide.cur], guide.gamma[1 - guide.cur]
         if ev is not None:
             ev[0].record()
@@ -107,7 +112,7 @@ def main():
             pg.reproject_sample(p, cur, prev, g_prev if t else None, g_out, guide.samples)
         if ev is not None:
             ev[1].record()
-        pg.light_field(guide.lights, cur, guide.vis, guide.samples)
+        pg.light_field(guide.lights, cur, dev_frames[t].vis, guide.samples)
         if ev is not None:
             ev[2].record()
         pg.em_update(p, cur, guide.samples, g_out)
@@ -150,7 +155,7 @@ def main():
 
     cpu = None
     if a.cpu_baseline_seconds > 0:
-        cpu = cpu_baseline(scene, seed, S, W, H, a.cpu_baseline_seconds)
+        cpu = cpu_baseline(seed, S, W, H, a.cpu_baseline_seconds)
 
     out = {
         "metric": "ms/frame & Mpix/s for reproject+sample+EM at 1080p 1spp; % of HBM roofline",
@@ -166,7 +171,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{W}x{H} spp{S}, {frames}-frame moving-camera sequence "
+            "workload": f"{W}x{H} spp{S}, {frames}-frame camera-pan sequence "
                         f"(timed frames {a.warmup}..{frames - 1}), Gamma {a.gamma_dtype}, "
                         f"{'unfused' if a.unfused else 'fused reproject+sample'}",
             "width": W, "height": H, "spp": S, "gamma_storage": a.gamma_dtype,
@@ -195,27 +200,28 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(scene, seed, spp, W, H, budget_s):
+def cpu_baseline(seed, spp, W, H, budget_s):
     """The FP64 oracle's reproject + sample + EM on the host cores (light field
     excluded like on the GPU): whole frames of the same sequence from frame 0
     until the time budget is spent."""
     import oracle as O
     from paper_2112_09728_amd import workload as wl
 
+    seq = wl.Sequence(W, H, seed, moving=True)
     v_prev = None
     gamma = None
     spent = 0.0
     n = 0
     t_all = time.time()
     while spent < budget_s and n < 64:
-        mv, mask = wl.make_motion(W, H, seed, n, moving=True)
-        v = O.OView(scene, mv, mask)
+        fr = seq.frame(n)
+        v = O.OView(fr, fr["motion"], fr["disocc"])
         P = O.params(seed, frame=n)
         t0 = time.time()
         g1, _ = O.reproject(P, v, v_prev if v_prev is not None else v, gamma)
         rec = O.sample(P, v, g1, spp)
         t1 = time.time()
-        rec["radiance"] = O.light(scene["lights"], float(scene["ambient"]), scene["vis"], rec["dir"],
+        rec["radiance"] = O.light(fr["lights"], float(fr["ambient"]), fr["vis"], rec["dir"],
                                   rec["strategy"])
         t2 = time.time()
         gamma = O.em(P, v, rec, g1)
@@ -232,7 +238,7 @@ def cpu_baseline(scene, seed, spp, W, H, budget_s):
         "ms_per_frame": round(ms, 1),
         "cores": O.num_threads(),
         "kind": "oracle",
-        "sample": f"frames 0..{n - 1} of the same {W}x{H} spp{spp} sequence, whole frames "
+        "sample": f"frames 0..{n - 1} of the same {W}x{H} spp{spp} pan sequence, whole frames "
                   f"({time.time() - t_all:.0f} s wall incl. the untimed light field)",
     }
 

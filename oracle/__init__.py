@@ -319,26 +319,27 @@ def num_threads():
 class Frames:
     """Plain frame sequence of the oracle: reproject -> sample -> light -> EM.
 
-    ``step`` returns the per-frame intermediates so a caller can compare them."""
+    ``step(t, fr)`` takes frame t's scene dict (G-buffer, lights, vis, motion,
+    disocc) and returns the per-frame intermediates."""
 
-    def __init__(self, scene, seed, spp, view=0, **kw):
-        self.scene = scene
+    def __init__(self, seed, spp, view=0, **kw):
         self.seed = seed
         self.spp = spp
         self.view_id = view
         self.kw = kw
         self.view_prev = None
         self.gamma = None
+        self.last = None
 
-    def step(self, frame, motion=None, disocc=None, rect=None, gamma_prev=None):
-        v = OView(self.scene, motion, disocc)
-        P = params(self.seed, frame=frame, view=self.view_id, **self.kw)
+    def step(self, t, fr, rect=None, gamma_prev=None):
+        v = OView(fr, fr.get("motion"), fr.get("disocc"))
+        P = params(self.seed, frame=t, view=self.view_id, **self.kw)
         gp = self.gamma if gamma_prev is None else gamma_prev
         prev = self.view_prev if self.view_prev is not None else v
         g1, src = reproject(P, v, prev, gp, rect=rect)
         rec = sample(P, v, g1, self.spp, rect=rect)
-        rec["radiance"] = light(self.scene["lights"], float(self.scene["ambient"]), self.scene["vis"],
-                                rec["dir"], rec["strategy"], rect=rect)
+        rec["radiance"] = light(fr["lights"], float(fr["ambient"]), fr["vis"], rec["dir"],
+                                rec["strategy"], rect=rect)
         g2 = em(P, v, rec, g1, rect=rect)
         self.gamma = g2
         self.view_prev = v

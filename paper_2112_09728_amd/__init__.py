@@ -295,4 +295,4 @@ def philox(counters, seed: int):
     return out
 
 
-from .guide import Guide, NLLFunction  # noqa: E402  (needs the names above)
+from .guide import DeviceFrame, Guide, NLLFunction  # noqa: E402  (needs the names above)

@@ -22,6 +22,13 @@ struct V3 {
 
 __device__ __forceinline__ float dot3(V3 a, V3 b) { return fmaf(a.z, b.z, fmaf(a.y, b.y, a.x * b.x)); }
 
+// Hardware square root and reciprocal (at most 1 ulp, normal inputs).  The
+// default HIP sqrtf and '/' are correctly rounded and several times longer;
+// the per-sample paths use these instead wherever the argument is known to
+// be a normal number.
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC 2011): ten rounds, two 32x32 -> 64-bit
 // multiplications per round, key bumped by the Weyl constants.
@@ -58,7 +65,7 @@ __device__ __forceinline__ Frame make_frame(V3 n) {
   const float inv = __builtin_amdgcn_rsqf(dot3(n, n));
   n = V3{n.x * inv, n.y * inv, n.z * inv};
   const float sign = copysignf(1.0f, n.z);
-  const float a = -1.0f / (sign + n.z);
+  const float a = -frcp(sign + n.z);  // sign + n.z lies in [1, 2]
   const float c = n.x * n.y * a;
   Frame f;
   f.t = V3{1.0f + sign * n.x * n.x * a, sign * c, -sign * n.x};
@@ -85,19 +92,21 @@ __device__ __forceinline__ V3 normalized(V3 v) {
 __device__ __forceinline__ V3 sq2hemi(float ux, float uy) {
   const float a = 2.0f * ux - 1.0f, b = 2.0f * uy - 1.0f;
   float r, q;
+  // a nonzero a or b is at least 2^-23 in magnitude, so the reciprocals
+  // below are of normal numbers
   if (fabsf(a) > fabsf(b)) {
     r = a;
-    q = 0.25f * (b / a);
+    q = 0.25f * b * frcp(a);
   } else if (b != 0.0f) {
     r = b;
-    q = 0.5f - 0.25f * (a / b);
+    q = 0.5f - 0.25f * a * frcp(b);
   } else {
     return V3{0.0f, 0.0f, 1.0f};
   }
   float s, c;
   sincospif(q, &s, &c);
   const float r2 = r * r;
-  const float k = r * sqrtf(2.0f - r2);
+  const float k = r * fsqrt(2.0f - r2);
   return V3{k * c, k * s, 1.0f - r2};
 }
 
@@ -119,27 +128,21 @@ __device__ __forceinline__ float atan_unit(float t) {
 }
 
 // M^-1 for a direction in the local frame with w.z >= 0 (|w| = 1 up to
-// rounding).  Squared disk radius (w_x^2 + w_y^2)/(1 + w_z) avoids the
-// cancellation of 1 - w_z; the disk angle inside each of the four concentric
-// sectors is atan of the ratio of the smaller to the larger of |w_x|, |w_y|
-// (the disk scaling cancels in that ratio).
+// rounding).  The disk radius is rho = sqrt((w_x^2 + w_y^2)/(1 + w_z)), which
+// avoids the cancellation of 1 - w_z; inside each of the four concentric
+// sectors the disk angle is atan of the ratio of the smaller to the larger of
+// w_x, w_y (the disk scaling cancels in that ratio).  Branch free.
 __device__ __forceinline__ void hemi2sq(V3 w, float &ux, float &uy) {
   const float s2 = fmaf(w.x, w.x, w.y * w.y);
-  const float rho = sqrtf(s2 * __builtin_amdgcn_rcpf(1.0f + w.z));
-  const float ax = fabsf(w.x), ay = fabsf(w.y);
-  float a, b;
-  if (ax > ay) {
-    a = copysignf(rho, w.x);
-    b = a * k4OverPi * atan_unit(w.y * __builtin_amdgcn_rcpf(w.x));
-  } else if (ay > 0.0f) {
-    b = copysignf(rho, w.y);
-    a = b * k4OverPi * atan_unit(w.x * __builtin_amdgcn_rcpf(w.y));
-  } else {
-    a = 0.0f;
-    b = 0.0f;
-  }
-  ux = fmaf(0.5f, a, 0.5f);
-  uy = fmaf(0.5f, b, 0.5f);
+  const float rho = s2 > 0.0f ? s2 * __builtin_amdgcn_rsqf(s2 * (1.0f + w.z)) : 0.0f;
+  const bool bigx = fabsf(w.x) > fabsf(w.y);
+  const float num = bigx ? w.y : w.x;
+  const float den = bigx ? w.x : w.y;
+  const float t = den != 0.0f ? num * __builtin_amdgcn_rcpf(den) : 0.0f;
+  const float r = copysignf(rho, den);
+  const float o = r * k4OverPi * atan_unit(t);
+  ux = fmaf(0.5f, bigx ? r : o, 0.5f);
+  uy = fmaf(0.5f, bigx ? o : r, 0.5f);
 }
 
 // ---------------------------------------------------------------------------
@@ -148,34 +151,42 @@ __device__ __forceinline__ void hemi2sq(V3 w, float &ux, float &uy) {
 // p_b = s_d wi_z/pi + (1 - s_d) D(h) h_z / (4 wo.h).
 struct Pixel {
   Frame f;
-  V3 wo;        // local view direction
-  float alpha2;  // alpha^2
+  V3 wo;            // local view direction
+  float alpha2;     // alpha^2
   float albedo_pi;  // albedo / pi
-  float g1_wo_over_4wo;  // G1(wo) / (4 wo_z)
-  float f0, s_d;
+  float a2_pi;      // alpha^2 / pi
+  float g1_wo_over_2wo;  // G1(wo) / (2 wo_z)
+  float f0, s_d, s_d_pi;
 };
 
 __device__ __forceinline__ float smith_g1(V3 v, float alpha2) {
-  return 2.0f * v.z / (v.z + sqrtf(fmaf(alpha2, fmaf(v.x, v.x, v.y * v.y), v.z * v.z)));
+  return 2.0f * v.z * frcp(v.z + fsqrt(fmaf(alpha2, fmaf(v.x, v.x, v.y * v.y), v.z * v.z)));
 }
 
-// f_r and p_b of a local direction wi with wi.z > 0.  h is unnormalised:
-// D(h/|h|) = alpha^2 |h|^4 / (pi (h_x^2 + h_y^2 + alpha^2 h_z^2)^2).
+// f_r and p_b of a local direction wi with wi.z > 0, one reciprocal in all.
+// With the unnormalised half vector h = wo + wi, den = h_x^2 + h_y^2 +
+// alpha^2 h_z^2 and q = sqrt(alpha^2 (wi_x^2 + wi_y^2) + wi_z^2):
+//   D(h/|h|)              = alpha^2 |h|^4 / (pi den^2)
+//   p_ggx = D h_z/(4 wo.h) = alpha^2 |h|^4 h_z / (4 pi den^2 (wo.h))
+//   G1(wi) / wi_z          = 2 / (wi_z + q)
+//   f_spec = F D G1(wi) G1(wo) / (4 wi_z wo_z) = F D (G1(wo)/(2 wo_z)) / (wi_z + q)
+// and R = 1 / (den^2 (wo.h) (wi_z + q)) serves both denominators.
 __device__ __forceinline__ void brdf_eval(const Pixel &px, V3 wi, float &f, float &pdf) {
   const V3 h = V3{px.wo.x + wi.x, px.wo.y + wi.y, px.wo.z + wi.z};
   const float hh = dot3(h, h);
   const float den = fmaf(px.alpha2, h.z * h.z, fmaf(h.x, h.x, h.y * h.y));
-  const float rden = __builtin_amdgcn_rcpf(den);
-  const float D = px.alpha2 * kInvPi * (hh * rden) * (hh * rden);
+  const float q = fsqrt(fmaf(px.alpha2, fmaf(wi.x, wi.x, wi.y * wi.y), wi.z * wi.z));
+  const float wq = wi.z + q;
   const float woh_u = dot3(px.wo, h);  // |h| (wo . h_hat)
-  const float pggx = D * h.z * __builtin_amdgcn_rcpf(4.0f * woh_u);
-  pdf = fmaf(px.s_d * kInvPi, wi.z, (1.0f - px.s_d) * pggx);
+  const float R = __builtin_amdgcn_rcpf(den * den * woh_u * wq);
+  const float A = px.a2_pi * hh * hh;  // D den^2
+  const float pggx = 0.25f * A * h.z * wq * R;
+  pdf = fmaf(px.s_d_pi, wi.z, (1.0f - px.s_d) * pggx);
   const float woh = woh_u * __builtin_amdgcn_rsqf(hh);
   const float m = 1.0f - woh;
   const float m2 = m * m;
   const float F = fmaf(1.0f - px.f0, m2 * m2 * m, px.f0);
-  const float g1wi = smith_g1(wi, px.alpha2);
-  f = fmaf(F * D * g1wi * px.g1_wo_over_4wo, __builtin_amdgcn_rcpf(wi.z), px.albedo_pi);
+  f = fmaf(F * A * px.g1_wo_over_2wo, woh_u * R, px.albedo_pi);
 }
 
 __device__ __forceinline__ float brdf_pdf_only(const Pixel &px, V3 wi) {
@@ -199,12 +210,14 @@ __device__ __forceinline__ Gauss gauss_setup(float mx, float my, float sxx, floa
   Gauss g;
   g.mx = mx;
   g.my = my;
-  g.l11 = sqrtf(fmaxf(sxx + eps, eps));
-  g.l21 = sxy / g.l11;
-  g.l22 = sqrtf(fmaxf((syy + eps) - g.l21 * g.l21, eps));
-  g.i11 = 1.0f / g.l11;
-  g.i22 = 1.0f / g.l22;
-  g.norm = kInv4Pi2 / (g.l11 * g.l22);
+  // the floors keep every argument a normal number when eps > 0
+  const float f = fmaxf(eps, 1.17549435e-38f);
+  g.l11 = fsqrt(fmaxf(sxx + eps, f));
+  g.i11 = frcp(g.l11);
+  g.l21 = sxy * g.i11;
+  g.l22 = fsqrt(fmaxf((syy + eps) - g.l21 * g.l21, f));
+  g.i22 = frcp(g.l22);
+  g.norm = kInv4Pi2 * g.i11 * g.i22;
   return g;
 }
 

@@ -59,9 +59,11 @@ __device__ __forceinline__ Pixel make_pixel(const ParamsK &P, V3 n, V3 o, float 
   const float alpha = rough * rough;
   px.alpha2 = alpha * alpha;
   px.albedo_pi = albedo * kInvPi;
-  px.g1_wo_over_4wo = smith_g1(px.wo, px.alpha2) / (4.0f * px.wo.z);
+  px.a2_pi = px.alpha2 * kInvPi;
+  px.g1_wo_over_2wo = smith_g1(px.wo, px.alpha2) * frcp(2.0f * px.wo.z);
   px.f0 = P.f0;
   px.s_d = P.s_d;
+  px.s_d_pi = P.s_d * kInvPi;
   return px;
 }
 
@@ -156,7 +158,7 @@ __device__ __forceinline__ void sample_pixel(const ParamsK &P, const ViewK &v, c
       float sn, cs;
       sincospif(2.0f * x2, &sn, &cs);
       if (zeta < pe) {
-        const float rho = sqrtf(-2.0f * logf(1.0f - x1));
+        const float rho = fsqrt(-2.0f * logf(1.0f - x1));
         const float z1 = rho * cs, z2 = rho * sn;
         const float ux = fmaf(G.l11, z1, G.mx);
         const float uy = fmaf(G.l22, z2, fmaf(G.l21, z1, G.my));
@@ -172,14 +174,15 @@ __device__ __forceinline__ void sample_pixel(const ParamsK &P, const ViewK &v, c
       } else {
         bool ok;
         if (xl < P.s_d) {
-          const float r = sqrtf(x1);
-          l = V3{r * cs, r * sn, sqrtf(1.0f - x1)};
+          const float r = fsqrt(x1);
+          l = V3{r * cs, r * sn, fsqrt(1.0f - x1)};
           ok = l.z > 0.0f;
           if (ok) pb = brdf_pdf_only(px, l);
         } else {
-          const float t2 = px.alpha2 * x1 / (1.0f - x1);
-          const float ch = 1.0f / sqrtf(1.0f + t2);
-          const float sh = sqrtf(t2) * ch;
+          // x1 <= 1 - 2^-24, so 1 - x1 and t2 (0 or >= alpha^2 2^-24) are normal
+          const float t2 = px.alpha2 * x1 * frcp(1.0f - x1);
+          const float ch = __builtin_amdgcn_rsqf(1.0f + t2);
+          const float sh = fsqrt(t2) * ch;
           const V3 h = V3{sh * cs, sh * sn, ch};
           const float woh = dot3(px.wo, h);
           l = V3{2.0f * woh * h.x - px.wo.x, 2.0f * woh * h.y - px.wo.y, 2.0f * woh * h.z - px.wo.z};
@@ -392,8 +395,9 @@ __device__ __forceinline__ void stage_records(const ViewK &v, const SamplesK &S,
 // weighted mean (mx, my) and normalised scatter (sxx, sxy, syy) of u under the
 // weights v = w gamma, updated per sample in the pairwise form
 //   m += (v / B1') d,   S = (B1 / B1') (S + (v / B1') d d^T),   d = u - m,
-// which has no cancellation when a heavy sample follows light ones and needs
-// no reciprocal of a (possibly subnormal) evidence.
+// which has no cancellation when a heavy sample follows light ones.  A
+// Gaussian weight below FP32's normal range counts as no evidence, so the
+// reciprocal of B1' is always of a normal number.
 struct Accum {
   float B0, B1, mx, my, sxx, sxy, syy;
 };
@@ -414,21 +418,13 @@ __device__ __forceinline__ void em_visit(const EmCtx &c, float4 r, Accum &a) {
   const float w = r.w * f * l.z;
   const float ga = c.pi * gauss_pdf_fast(c.G, ux, uy);
   const float gb = c.one_m_pi * pb;
-  const float sum = ga + gb;
-  const float gam = sum > 0.0f ? ga / sum : 0.0f;
+  const float gam = ga * __builtin_amdgcn_rcpf(fmaxf(ga + gb, 1.17549435e-38f));
   a.B0 += w;
   const float vw = w * gam;
-  if (vw > 0.0f) {
+  if (vw >= 1.17549435e-38f) {
     const float bn = a.B1 + vw;
-    float fr, keep;
-    if (bn >= 1.17549435e-38f) {
-      const float rb = __builtin_amdgcn_rcpf(bn);
-      fr = vw * rb;
-      keep = a.B1 * rb;
-    } else {
-      fr = vw / bn;
-      keep = a.B1 / bn;
-    }
+    const float rb = __builtin_amdgcn_rcpf(bn);
+    const float fr = vw * rb, keep = a.B1 * rb;
     a.B1 = bn;
     const float dx = ux - a.mx, dy = uy - a.my;
     a.mx = fmaf(dx, fr, a.mx);
@@ -456,47 +452,114 @@ __device__ __forceinline__ int pick_index(uint4 w4, int m, int spp, uint32_t cs,
   return s * SA + (ly + kR + dy) * SW + (lx + kR + dx);
 }
 
+// Training list of one pixel: the LDS indices of its kept candidates, in the
+// order of the training set (own samples by sample index, then picks by pick
+// index).  A candidate is kept when its staged record is a BRDF-strategy
+// sample inside the image.  Returns the list length.
+template <int TW, int TH>
+__device__ __forceinline__ int build_list(const ParamsK &P, const float4 *lds, uint16_t *list, int lane,
+                                          int lx, int ly, int k, int spp, uint32_t pix) {
+  constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH, NT = TW * TH;
+  k = k < 0 ? 0 : (k > P.k_max ? P.k_max : k);
+  const int npick = 5 + (15 * (P.k_max - k)) / P.k_max;
+  const uint32_t cs = (uint32_t)(kCand * spp);
+  const uint32_t inv_spp = (65536u + (uint32_t)spp - 1u) / (uint32_t)spp;
+  const int own = (ly + kR) * SW + (lx + kR);
+  int n = 0;
+  for (int s = 0; s < spp; ++s) {
+    const int e = s * SA + own;
+    if (lds[e].w != 0.0f) list[(n++) * NT + lane] = (uint16_t)e;
+  }
+  uint4 w4 = make_uint4(0, 0, 0, 0);
+  for (int m = 0; m < npick; ++m) {
+    if ((m & 7) == 0) w4 = philox4x32_10(pix, P.frame, (1u << 16) | (uint32_t)(m >> 3), P.view, P.key0, P.key1);
+    const int e = pick_index<SW, SA>(w4, m, spp, cs, inv_spp, lx, ly);
+    if (lds[e].w != 0.0f) list[(n++) * NT + lane] = (uint16_t)e;
+  }
+  return n;
+}
+
+// Order the tile's pixels by decreasing work `len` (0 .. kMaxLen - 1) so that
+// the lanes of a wave carry nearly equal work (the order inside a class is
+// irrelevant: a pixel's arithmetic does not depend on the lane it runs on).
+// Returns the tile-local pixel index this lane works on.
+constexpr int kMaxLen = kMaxSpp + 21;
+
+template <int NT>
+__device__ __forceinline__ int balance(int len, int *cnt, int *perm) {
+  const int t = threadIdx.x;
+  if (t < kMaxLen) cnt[t] = 0;
+  __syncthreads();
+  const int rank = atomicAdd(&cnt[len], 1);
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int b = kMaxLen - 1; b >= 0; --b) {
+      const int c = cnt[b];
+      cnt[b] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+  perm[cnt[len] + rank] = t;
+  __syncthreads();
+  return perm[t];
+}
+
 template <typename TG, int TW, int TH>
 __global__ __launch_bounds__(TW *TH) void k_em(ParamsK P, ViewK v, SamplesK S, TG *__restrict__ gamma,
                                                int iterations, int batch, int tiles_x, int n_tiles) {
-  extern __shared__ float4 lds[];
-  constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH;
+  constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH, NT = TW * TH;
+  extern __shared__ float4 lds[];  // records [spp][SH][SW], then lists [spp + 20][NT]
+  __shared__ int s_cnt[kMaxLen];
+  __shared__ int s_perm[NT];
+  uint16_t *list = reinterpret_cast<uint16_t *>(lds + S.spp * SA);
   const int tile = xcd_tile(blockIdx.x, n_tiles);
   const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
   stage_records<TW, TH>(v, S, lds, tx0, ty0);
-  __syncthreads();
-  const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+  const int plane = v.H * v.pitch;
+  // natural pixel order: the number of candidates of this lane's pixel
+  // (0 when it is not trained)
+  int ncand = 0;
+  {
+    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int x = tx0 + lx, y = ty0 + ly;
+    if (x < v.W && y < v.H) {
+      const int idx = y * v.pitch + x;
+      const bool guided = dot3(load3(v.n, plane, idx), load3(v.o, plane, idx)) > 0.0f &&
+                          v.rough[idx] >= P.rough_min;
+      if (guided) {
+        int kk = (int)GammaIO<TG>::load(gamma + 7 * plane + idx);
+        kk = kk < 0 ? 0 : (kk > P.k_max ? P.k_max : kk);
+        ncand = S.spp + 5 + (15 * (P.k_max - kk)) / P.k_max;
+      }
+    }
+  }
+  // pixels by decreasing candidate count; the barriers inside also publish
+  // the staged records
+  const int me = balance<NT>(ncand, s_cnt, s_perm);
+  const int lx = me % TW, ly = me / TW;
   const int x = tx0 + lx, y = ty0 + ly;
   if (x >= v.W || y >= v.H) return;
-  const int plane = v.H * v.pitch;
   const int idx = y * v.pitch + x;
-  const V3 n = load3(v.n, plane, idx);
-  const V3 o = load3(v.o, plane, idx);
-  const float rough = v.rough[idx];
-  if (!(dot3(n, o) > 0.0f && rough >= P.rough_min)) return;
   float g[8];
   gamma_load(gamma, plane, idx, g);
+  const V3 n = load3(v.n, plane, idx), o = load3(v.o, plane, idx);
+  const float rough = v.rough[idx];
+  if (!(dot3(n, o) > 0.0f && rough >= P.rough_min)) return;
+  // training list of this pixel, kept in this lane's column of the list area
+  const int len = build_list<TW, TH>(P, lds, list, threadIdx.x, lx, ly, (int)g[7], S.spp,
+                                     (uint32_t)(y * v.W + x));
+  if (len == 0) return;  // no training sample: the model stays as it is
   EmCtx c;
   c.px = make_pixel(P, n, o, rough, v.alb[idx]);
-  int k = (int)g[7];
-  k = k < 0 ? 0 : (k > P.k_max ? P.k_max : k);
-  const int npick = 5 + (15 * (P.k_max - k)) / P.k_max;
-  const uint32_t pix = (uint32_t)(y * v.W + x);
-  const uint32_t cs = (uint32_t)(kCand * S.spp);
-  const uint32_t inv_spp = (65536u + (uint32_t)S.spp - 1u) / (uint32_t)S.spp;
-  const int own = (ly + kR) * SW + (lx + kR);
   const int iters = batch ? iterations : 1;
   for (int it = 0; it < iters; ++it) {
     c.G = gauss_setup(g[0], g[1], g[2], g[3], g[4], P.eps);
     c.pi = g[5];
     c.one_m_pi = 1.0f - g[5];
     Accum a = {0, 0, 0, 0, 0, 0, 0};
-    for (int s = 0; s < S.spp; ++s) em_visit(c, lds[s * SA + own], a);
-    uint4 w4 = make_uint4(0, 0, 0, 0);
-    for (int m = 0; m < npick; ++m) {
-      if ((m & 7) == 0) w4 = philox4x32_10(pix, P.frame, (1u << 16) | (uint32_t)(m >> 3), P.view, P.key0, P.key1);
-      em_visit(c, lds[pick_index<SW, SA>(w4, m, S.spp, cs, inv_spp, lx, ly)], a);
-    }
+    for (int j = 0; j < len; ++j) em_visit(c, lds[list[j * NT + threadIdx.x]], a);
     if (!(a.B0 > 0.0f)) break;
     if (!batch) {
       // stepwise merge with eta = 1/(k+1) and evidence W; only ratios of

@@ -143,11 +143,16 @@ pg_status dispatch_dtype(int dtype, F &&f) {
 struct Tile {
   int w, h;
 };
-constexpr Tile kTiles[] = {{32, 8}, {16, 16}, {64, 4}, {32, 4}, {16, 8}, {64, 2}};
+constexpr Tile kTiles[] = {{32, 8}, {16, 16}, {64, 4}, {32, 4}, {16, 8}, {64, 2}, {32, 16}, {64, 8}};
 
 Tile default_tile(int spp) { return spp <= 4 ? Tile{32, 8} : Tile{32, 4}; }
 
-size_t tile_lds(Tile t, int spp) { return (size_t)(t.w + 2 * kR) * (t.h + 2 * kR) * spp * sizeof(float4); }
+// Dynamic LDS of the training kernels: staged records [spp][h+6][w+6] float4
+// and the per-pixel training lists [spp+20][w*h] uint16.
+size_t tile_lds(Tile t, int spp) {
+  return (size_t)(t.w + 2 * kR) * (t.h + 2 * kR) * spp * sizeof(float4) +
+         (size_t)(spp + 20) * t.w * t.h * sizeof(uint16_t);
+}
 
 pg_status pick_tile(const pg_params *p, int spp, Tile &t) {
   if (p->tile_w == 0 && p->tile_h == 0) {
@@ -170,7 +175,7 @@ void launch_em_t(const ParamsK &P, const ViewK &v, const SamplesK &S, TG *g, int
                  hipStream_t st) {
   const int tx = (v.W + TW - 1) / TW, ty = (v.H + TH - 1) / TH;
   const int n = tx * ty;
-  const size_t lds = (size_t)(TW + 2 * kR) * (TH + 2 * kR) * S.spp * sizeof(float4);
+  const size_t lds = tile_lds(Tile{TW, TH}, S.spp);
   hipLaunchKernelGGL((k_em<TG, TW, TH>), dim3(n), dim3(TW * TH), lds, st, P, v, S, g, iters, batch, tx, n);
 }
 
@@ -182,6 +187,8 @@ void launch_em(Tile t, const ParamsK &P, const ViewK &v, const SamplesK &S, TG *
   else if (t.w == 64 && t.h == 4) launch_em_t<TG, 64, 4>(P, v, S, g, iters, batch, st);
   else if (t.w == 32 && t.h == 4) launch_em_t<TG, 32, 4>(P, v, S, g, iters, batch, st);
   else if (t.w == 16 && t.h == 8) launch_em_t<TG, 16, 8>(P, v, S, g, iters, batch, st);
+  else if (t.w == 32 && t.h == 16) launch_em_t<TG, 32, 16>(P, v, S, g, iters, batch, st);
+  else if (t.w == 64 && t.h == 8) launch_em_t<TG, 64, 8>(P, v, S, g, iters, batch, st);
   else launch_em_t<TG, 64, 2>(P, v, S, g, iters, batch, st);
 }
 
@@ -201,6 +208,8 @@ void launch_nll(Tile t, const ParamsK &P, const ViewK &v, const SamplesK &S, con
   else if (t.w == 64 && t.h == 4) launch_nll_t<64, 4>(P, v, S, theta, go, grad, nll, st);
   else if (t.w == 32 && t.h == 4) launch_nll_t<32, 4>(P, v, S, theta, go, grad, nll, st);
   else if (t.w == 16 && t.h == 8) launch_nll_t<16, 8>(P, v, S, theta, go, grad, nll, st);
+  else if (t.w == 32 && t.h == 16) launch_nll_t<32, 16>(P, v, S, theta, go, grad, nll, st);
+  else if (t.w == 64 && t.h == 8) launch_nll_t<64, 8>(P, v, S, theta, go, grad, nll, st);
   else launch_nll_t<64, 2>(P, v, S, theta, go, grad, nll, st);
 }
 

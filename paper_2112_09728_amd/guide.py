@@ -14,24 +14,39 @@ from . import (PgParams, Samples, View, em_update, light_field, lights_struct, n
                reproject, reproject_sample, sample_mis, nll_backward)
 
 
+class DeviceFrame:
+    """One frame's inputs resident on the device: the G-buffer view (with
+    motion and disocclusion) and the light-visibility bits."""
+
+    def __init__(self, fr: dict, device="cuda"):
+        import numpy as np
+
+        def dev(a):
+            return None if a is None else torch.as_tensor(np.ascontiguousarray(a)).to(device)
+        self.view = View(dev(fr["normal"]), dev(fr["view_dir"]), dev(fr["depth"]),
+                         dev(fr["roughness"]), dev(fr["albedo"]), dev(fr.get("motion")),
+                         dev(fr.get("disocc")))
+        self.vis = dev(fr["vis"])
+
+
 class Guide:
-    def __init__(self, scene: dict, spp: int = 1, seed: int | None = None, view_id: int = 0,
-                 gamma_dtype=torch.float32, fused: bool = True, device="cuda", **param_overrides):
-        self.scene = scene
+    """Per-view state of the path (two Gamma buffers used in turn, the sample
+    records) and one frame of it per ``step``."""
+
+    def __init__(self, width: int, height: int, lights, ambient, spp: int = 1, seed: int = 0,
+                 view_id: int = 0, gamma_dtype=torch.float32, fused: bool = True, device="cuda",
+                 **param_overrides):
+        self.width, self.height = width, height
         self.spp = spp
-        self.seed = scene.get("seed", 0) if seed is None else seed
+        self.seed = seed
         self.view_id = view_id
         self.fused = fused
         self.overrides = param_overrides
-        H, W = scene["height"], scene["width"]
-        self.base = View.from_scene(scene, device)
-        # previous-frame G-buffer kept in its own memory, as a renderer would
-        self.prev_base = View.from_scene(scene, device)
-        self.vis = torch.as_tensor(scene["vis"]).to(device).contiguous()
-        self.lights = lights_struct(scene["lights"], float(scene["ambient"]))
-        self.gamma = [new_gamma(H, W, gamma_dtype, device), new_gamma(H, W, gamma_dtype, device)]
+        self.lights = lights_struct(lights, ambient)
+        self.gamma = [new_gamma(height, width, gamma_dtype, device),
+                      new_gamma(height, width, gamma_dtype, device)]
         self.cur = 0
-        self.samples = Samples(spp, H, W, device)
+        self.samples = Samples(spp, height, width, device)
         self.frame = 0
 
     def params(self, frame: int) -> PgParams:
@@ -41,23 +56,19 @@ class Guide:
     def state(self):
         return self.gamma[self.cur]
 
-    def view_for(self, motion, disocc) -> View:
-        return self.base.with_motion(motion, disocc)
-
-    def step(self, motion=None, disocc=None, frame: int | None = None):
+    def step(self, cur: DeviceFrame, prev: DeviceFrame | None, frame: int | None = None):
         """One frame on the current stream; returns the updated Gamma tensor."""
         t = self.frame if frame is None else frame
         p = self.params(t)
-        cur = self.view_for(motion, disocc)
-        prev = self.prev_base if t > 0 else None
+        pv = prev.view if (prev is not None and t > 0) else None
         g_prev, g_out = self.gamma[self.cur], self.gamma[1 - self.cur]
         if self.fused:
-            reproject_sample(p, cur, prev, g_prev if t > 0 else None, g_out, self.samples)
+            reproject_sample(p, cur.view, pv, g_prev if t > 0 else None, g_out, self.samples)
         else:
-            reproject(p, cur, prev, g_prev if t > 0 else None, g_out)
-            sample_mis(p, cur, g_out, self.samples)
-        light_field(self.lights, cur, self.vis, self.samples)
-        em_update(p, cur, self.samples, g_out)
+            reproject(p, cur.view, pv, g_prev if t > 0 else None, g_out)
+            sample_mis(p, cur.view, g_out, self.samples)
+        light_field(self.lights, cur.view, cur.vis, self.samples)
+        em_update(p, cur.view, self.samples, g_out)
         self.cur = 1 - self.cur
         self.frame = t + 1
         return g_out

@@ -11,8 +11,14 @@ traced radiance with seeded synthetic data of the same shape:
 * three spherical-Gaussian lights (axis uniform on the upper hemisphere,
   sharpness U[10, 200], intensity U[1, 20]), ambient 0.05, and a binary
   visibility bit per (pixel, light) with probability 1/2;
-* per frame: motion vectors U[-2, 2]^2 px quantised to 1/256 px and a 2%
-  disocclusion mask (none at frame 0).
+* per frame (``Sequence``): a camera pan.  The G-buffer is a window onto a
+  larger world texture; the window moves by a step drawn from U[-2, 2]^2 px
+  (quantised to 1/256 px) each frame, so every pixel's motion vector is the
+  pan step, the G-buffer of frame t is the nearest world texel under each
+  pixel, and a 2% disocclusion mask (none at frame 0) marks pixels whose
+  history is discarded.  ``make_motion`` instead draws independent motion
+  per pixel over a static G-buffer, a harder case for the reprojection
+  gather used by the tests.
 
 This module holds no arithmetic of the method itself: it only draws inputs.
 Both the GPU path and the CPU oracle consume the arrays it returns.
@@ -63,10 +69,14 @@ def _value_noise(width: int, height: int, cell: float, rng: np.random.Generator)
     return h, dx, dy
 
 
-def make_scene(width: int, height: int, seed: int) -> dict:
+def make_scene(width: int, height: int, seed: int, margin: int = 0) -> dict:
     """Static G-buffer, lights and visibility of one synthetic view.
 
-    Arrays are float32 (uint8 for ``vis``), laid out [channel][H][W]."""
+    Arrays are float32 (uint8 for ``vis``), laid out [channel][H][W].  With a
+    margin the surface arrays cover (H + 2 margin) x (W + 2 margin) texels
+    while the view direction stays that of the W x H screen."""
+    sw, sh = width, height
+    width, height = width + 2 * margin, height + 2 * margin
     rng_h = _rng(seed, _S_HEIGHT)
     h = np.zeros((height, width))
     gx = np.zeros((height, width))
@@ -88,11 +98,11 @@ def make_scene(width: int, height: int, seed: int) -> dict:
     n = np.stack([-gx, -gy, np.ones_like(gx)])
     n /= np.sqrt((n * n).sum(0, keepdims=True))
     depth = 1000.0 - h
-    xs = np.arange(width) + 0.5
-    ys = np.arange(height) + 0.5
-    cam_h = float(max(width, height))
-    vd = np.stack(np.broadcast_arrays(width / 2.0 - xs[None, :], height / 2.0 - ys[:, None],
-                                      np.full((height, width), cam_h)))
+    xs = np.arange(sw) + 0.5
+    ys = np.arange(sh) + 0.5
+    cam_h = float(max(sw, sh))
+    vd = np.stack(np.broadcast_arrays(sw / 2.0 - xs[None, :], sh / 2.0 - ys[:, None],
+                                      np.full((sh, sw), cam_h)))
     vd = vd / np.sqrt((vd * vd).sum(0, keepdims=True))
     rng_m = _rng(seed, _S_MATERIAL)
     roughness = rng_m.uniform(0.05, 1.0, size=(height, width))
@@ -111,7 +121,7 @@ def make_scene(width: int, height: int, seed: int) -> dict:
     for k in range(N_LIGHTS):
         vis |= bits[k] << k
     return dict(
-        width=width, height=height, seed=seed,
+        width=sw, height=sh, seed=seed, margin=margin,
         normal=n.astype(np.float32),
         view_dir=vd.astype(np.float32),
         depth=depth.astype(np.float32),
@@ -133,6 +143,56 @@ def make_motion(width: int, height: int, seed: int, frame: int, moving: bool = T
     rng_m = _rng(seed, _S_MASK, frame)
     mask = (rng_m.uniform(0.0, 1.0, size=(height, width)) < disocc_rate).astype(np.uint8)
     return mv.astype(np.float32), mask
+
+
+class Sequence:
+    """Frames of a camera pan over a static world (see the module docstring).
+
+    ``frame(t)`` returns a scene dict for frame t with ``motion`` [2][H][W]
+    (px, current minus previous position, the same for every pixel) and
+    ``disocc`` [H][W]; frames must be requested in order 0, 1, 2, ..."""
+
+    def __init__(self, width: int, height: int, seed: int, moving: bool = True,
+                 disocc_rate: float = 0.02, margin: int = 64):
+        self.width, self.height, self.seed = width, height, seed
+        self.moving, self.disocc_rate, self.margin = moving, disocc_rate, margin
+        self.world = make_scene(width, height, seed, margin=margin if moving else 0)
+        self.offset = np.zeros(2)
+        self.t = -1
+
+    def _window(self, ox: float, oy: float) -> dict:
+        W, H, M = self.width, self.height, self.world["margin"]
+        ix = np.floor(np.arange(W) + 0.5 + ox).astype(np.int64) + M
+        iy = np.floor(np.arange(H) + 0.5 + oy).astype(np.int64) + M
+        out = dict(self.world)
+        out["width"], out["height"] = W, H
+        for key in ("normal",):
+            out[key] = np.ascontiguousarray(self.world[key][:, iy[:, None], ix[None, :]])
+        for key in ("depth", "roughness", "albedo", "vis"):
+            out[key] = np.ascontiguousarray(self.world[key][iy[:, None], ix[None, :]])
+        return out
+
+    def frame(self, t: int) -> dict:
+        if t != self.t + 1:
+            raise ValueError("frames of a Sequence are generated in order")
+        self.t = t
+        W, H = self.width, self.height
+        step = np.zeros(2)
+        mask = np.zeros((H, W), np.uint8)
+        if self.moving and t > 0:
+            rng = _rng(self.seed, _S_MOTION, t)
+            step = np.round(rng.uniform(-2.0, 2.0, size=2) * 256.0) / 256.0
+            lim = self.margin - 3
+            new = np.clip(self.offset + step, -lim, lim)
+            step = new - self.offset
+            self.offset = new
+            rng_m = _rng(self.seed, _S_MASK, t)
+            mask = (rng_m.uniform(0.0, 1.0, size=(H, W)) < self.disocc_rate).astype(np.uint8)
+        out = self._window(*self.offset)
+        # content moves opposite to the window: motion = -(window step)
+        out["motion"] = np.broadcast_to((-step).astype(np.float32)[:, None, None], (2, H, W)).copy()
+        out["disocc"] = mask
+        return out
 
 
 def crop_scene(scene: dict, x0: int, y0: int, x1: int, y1: int) -> dict:

@@ -214,20 +214,20 @@ def compare_samples(rec_gpu, rec_orc, pix_mask=None, scene=None, gamma=None):
 class GpuFrames:
     """The GPU path frame by frame, keeping every intermediate on request."""
 
-    def __init__(self, scene, spp, seed, gamma_dtype=torch.float32, fused=True, view_id=0,
-                 **over):
-        self.g = pg.Guide(scene, spp=spp, seed=seed, view_id=view_id, gamma_dtype=gamma_dtype,
-                          fused=fused, **over)
+    def __init__(self, width, height, lights, ambient, spp, seed, gamma_dtype=torch.float32,
+                 fused=True, view_id=0, **over):
+        self.g = pg.Guide(width, height, lights, ambient, spp=spp, seed=seed, view_id=view_id,
+                          gamma_dtype=gamma_dtype, fused=fused, **over)
+        self.prev = None
 
-    def step(self, t, mv, mask, keep=True):
+    def step(self, t, fr, keep=True):
+        cur = pg.DeviceFrame(fr)
         g_prev = self.g.state.clone() if keep else None
-        out = self.g.step(dev(mv), dev(mask), frame=t)
+        out = self.g.step(cur, self.prev, frame=t)
+        self.prev = cur
         torch.cuda.synchronize()
         if not keep:
             return None
-        # Gamma' (after reprojection, before EM) is recomputed by pg_reproject
-        # for the record; the fused kernel wrote it into the output buffer
-        # before EM updated it in place.
         return dict(gamma_prev=host(g_prev), gamma=host(out), rec=records_host(self.g.samples))
 
 

@@ -1,0 +1,113 @@
+"""Gamma stored as FP16 / BF16 with FP32 arithmetic.
+
+Implementation parity: each frame is stepped teacher-forced from the GPU's
+stored state by a storage-rounding oracle (the FP64 oracle with its state
+rounded to the format at every store, as the kernels do) and must agree to
+about one unit in the last place of the format.  Format error: the free
+running FP16/BF16 states against the unrounded FP64 oracle, printed as a table
+per parameter."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2112_09728_amd as pg
+from paper_2112_09728_amd import workload as wl
+from pgtest import (GpuFrames, compare_samples, gamma_errors, host, rel_err, TOL_DIR,
+                    underflow_mask)
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+FMT = {"f16": (torch.float16, 65504.0, 10), "bf16": (torch.bfloat16, 3.38953139e38, 7)}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def round_storage(g, fmt):
+    """Round a state to the storage format (nearest even; W saturates)."""
+    g = np.asarray(g, np.float64).copy()
+    _, vmax, _ = FMT[fmt]
+    g[6] = np.minimum(g[6], vmax)
+    if fmt == "f16":
+        return g.astype(np.float16).astype(np.float64)
+    f = g.astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def ulp(v, fmt):
+    """One unit in the last place of the format at |v| (subnormal floor)."""
+    _, _, mant = FMT[fmt]
+    v = np.maximum(np.abs(np.asarray(v, np.float64)), 2.0 ** -14 if fmt == "f16" else 2.0 ** -126)
+    return 2.0 ** (np.floor(np.log2(v)) - mant)
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_lowprec_frames_match_storage_rounding_oracle(fmt):
+    say(f"case: {fmt} frames")
+    W, H, spp, seed = 80, 56, 1, wl.SEED_BASE + 3
+    seq = wl.Sequence(W, H, seed)
+    fr = seq.frame(0)
+    dt = FMT[fmt][0]
+    gf = GpuFrames(W, H, fr["lights"], fr["ambient"], spp, seed, gamma_dtype=dt)
+    v_prev = None
+    for t in range(6):
+        if t:
+            fr = seq.frame(t)
+        r = gf.step(t, fr)
+        P = O.params(seed, frame=t)
+        v = O.OView(fr, fr["motion"], fr["disocc"])
+        g1, _ = O.reproject(P, v, v_prev if v_prev is not None else v, r["gamma_prev"] if t else None)
+        g1 = round_storage(g1, fmt)
+        ro = O.sample(P, v, g1, spp)
+        st, _ = compare_samples(r["rec"], ro, scene=fr, gamma=g1)
+        assert st["dir_max"] <= TOL_DIR
+        g2, stats = O.em(P, v, r["rec"], g1, with_stats=True)
+        g2r = round_storage(g2, fmt)
+        ok = ~underflow_mask(stats)
+        d = np.abs(r["gamma"] - g2r)
+        # one format ulp of the value, plus the FP32 arithmetic's share
+        bound = ulp(g2r, fmt) + 1e-5 * (np.abs(g2r) + 1e-3)
+        over = (d > bound) & ok[None]
+        say(f"  frame {t}: channels beyond 1 ulp: {int(over.sum())} of {over.size}; "
+            f"max d/ulp {float((d / ulp(g2r, fmt))[:, ok].max()):.2f}")
+        assert over.sum() <= 1e-3 * over.size
+        assert (r["gamma"][7] == g2r[7]).all()
+        v_prev = v
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_lowprec_error_table_against_fp64(fmt):
+    """Free-running FP16/BF16 states against the unrounded FP64 oracle after
+    8 frames: the error of each stored parameter, printed as a table."""
+    say(f"case: {fmt} error table")
+    W, H, spp, seed = 96, 64, 1, wl.SEED_BASE + 3
+    seq = wl.Sequence(W, H, seed, moving=False)
+    fr0 = seq.frame(0)
+    gf = GpuFrames(W, H, fr0["lights"], fr0["ambient"], spp, seed, gamma_dtype=FMT[fmt][0])
+    g32 = GpuFrames(W, H, fr0["lights"], fr0["ambient"], spp, seed)
+    of = O.Frames(seed=seed, spp=spp)
+    fr = fr0
+    for t in range(8):
+        if t:
+            fr = seq.frame(t)
+        gf.step(t, fr, keep=False)
+        g32.step(t, fr, keep=False)
+        of.step(t, fr)
+    torch.cuda.synchronize()
+    gl, gs = host(gf.g.state).astype(np.float64), host(g32.g.state).astype(np.float64)
+    go = of.gamma
+    for name, g in ((fmt, gl), ("f32", gs)):
+        e = gamma_errors(g, go)
+        say(f"  {name:5s} vs FP64 after 8 frames: " + ", ".join(
+            f"{k} max {float(v.max()):.2e} median {float(np.median(v)):.2e}" for k, v in e.items()))
+    e = gamma_errors(gl, go)
+    assert (e["k"] == 0).mean() > 0.99
+    lim = 2e-2 if fmt == "bf16" else 2e-3
+    assert np.median(e["mu"]) <= lim and np.median(e["pi"]) <= lim

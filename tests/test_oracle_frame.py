@@ -370,26 +370,41 @@ def test_em_trains_on_brdf_samples_only():
 def test_oracle_crop_equals_full_frame():
     """A rectangle computed alone equals the same rectangle of the full frame."""
     sc = wl.make_scene(40, 30, 51)
-    f_full = O.Frames(sc, seed=51, spp=2)
-    f_crop = O.Frames(sc, seed=51, spp=2)
-    rect = (8, 6, 30, 22)
+    frames = [dict(sc, motion=m[0], disocc=m[1]) for m in
+              (wl.make_motion(40, 30, 51, t) for t in range(3))]
+    f_full = O.Frames(seed=51, spp=2)
     for t in range(3):
-        mv, m = wl.make_motion(40, 30, 51, t)
-        a = f_full.step(t, mv, m)
-        b = f_crop.step(t, mv, m)
-    # the crop's dependency cone: recompute with the crop only in the last frame
-    f_c = O.Frames(sc, seed=51, spp=2)
+        a = f_full.step(t, frames[t])
+    f_c = O.Frames(seed=51, spp=2)
     for t in range(2):
-        mv, m = wl.make_motion(40, 30, 51, t)
-        f_c.step(t, mv, m)
-    mv, m = wl.make_motion(40, 30, 51, 2)
-    gp = f_c.gamma
-    v = O.OView(sc, mv, m)
+        f_c.step(t, frames[t])
+    rect = (8, 6, 30, 22)
+    fr = frames[2]
+    v = O.OView(fr, fr["motion"], fr["disocc"])
     P = O.params(51, frame=2)
-    g1, _ = O.reproject(P, v, f_c.view_prev, gp)
+    g1, _ = O.reproject(P, v, f_c.view_prev, f_c.gamma)
     rec = O.sample(P, v, g1, 2)
     rec["radiance"] = O.light(sc["lights"], float(sc["ambient"]), sc["vis"], rec["dir"],
                               rec["strategy"])
     g2 = O.em(P, v, rec, g1, rect=rect)
     x0, y0, x1, y1 = rect
     assert (g2[:, y0:y1, x0:x1] == a["gamma"][:, y0:y1, x0:x1]).all()
+
+
+def test_pan_sequence_reprojects_onto_the_same_surface():
+    """In the camera-pan workload most histories are found (only the
+    disoccluded, unguided and border pixels start new models) and the
+    source texel is the same world texel for nearly every pixel."""
+    W, H = 48, 40
+    seq = wl.Sequence(W, H, 61)
+    f0 = seq.frame(0)
+    f1 = seq.frame(1)
+    v0 = O.OView(f0)
+    v1 = O.OView(f1, f1["motion"], f1["disocc"])
+    g = np.tile(np.array([0.5, 0.5, 0.01, 0, 0.01, 0.3, 1.0, 3.0])[:, None, None], (1, H, W))
+    g1, src = O.reproject(O.params(61, frame=1), v1, v0, g)
+    guided = (f1["roughness"] >= np.float32(0.1)) & (f1["disocc"] == 0)
+    assert (src[guided] >= 0).mean() > 0.9
+    qy, qx = np.divmod(src[src >= 0], W)
+    same = (f0["roughness"][qy, qx] == f1["roughness"][src >= 0])
+    assert same.mean() > 0.9
