@@ -40,13 +40,14 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    // one 32x32 -> 64-bit multiply (v_mad_u64_u32) gives both halves
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
     c0 = n0;
-    c1 = lo1;
+    c1 = (uint32_t)p1;
     c2 = n2;
-    c3 = lo0;
+    c3 = (uint32_t)p0;
   }
   return make_uint4(c0, c1, c2, c3);
 }
@@ -84,6 +85,33 @@ __device__ __forceinline__ V3 normalized(V3 v) {
   return V3{v.x * inv, v.y * inv, v.z * inv};
 }
 
+// sin(pi t) and cos(pi t) for |t| <= 2: t = r + j/2 with |r| <= 1/4, Taylor
+// series of sin and cos at pi r (|pi r| <= pi/4: truncation below 2e-9, about
+// 1 ulp in FP32), then the quarter turn j.
+__device__ __forceinline__ void sincospi_small(float t, float *s, float *c) {
+  const float j = rintf(2.0f * t);
+  const float r = fmaf(-0.5f, j, t);
+  const float r2 = r * r;
+  // sin(pi r) = r (pi - pi^3 r^2/3! + pi^5 r^4/5! - pi^7 r^6/7! + pi^9 r^8/9!)
+  float ps = 8.21458866e-02f;
+  ps = fmaf(ps, r2, -5.99264529e-01f);
+  ps = fmaf(ps, r2, 2.55016404e+00f);
+  ps = fmaf(ps, r2, -5.16771278e+00f);
+  ps = fmaf(ps, r2, 3.14159265e+00f);
+  const float sr = r * ps;
+  // cos(pi r) = 1 - pi^2 r^2/2! + pi^4 r^4/4! - pi^6 r^6/6! + pi^8 r^8/8! - pi^10 r^10/10!
+  float pc = -2.58068914e-02f;
+  pc = fmaf(pc, r2, 2.35330630e-01f);
+  pc = fmaf(pc, r2, -1.33526277e+00f);
+  pc = fmaf(pc, r2, 4.05871213e+00f);
+  pc = fmaf(pc, r2, -4.93480220e+00f);
+  const float cr = fmaf(pc, r2, 1.0f);
+  const int q = ((int)j) & 3;
+  const float ss = (q & 1) ? cr : sr, cc = (q & 1) ? sr : cr;
+  *s = (q & 2) ? -ss : ss;
+  *c = ((q + 1) & 2) ? -cc : cc;
+}
+
 // ---------------------------------------------------------------------------
 // M: unit square -> upper hemisphere.  Concentric square-to-disk map of
 // Shirley and Chiu (JGT 1997) followed by the equal-area lift
@@ -104,7 +132,7 @@ __device__ __forceinline__ V3 sq2hemi(float ux, float uy) {
     return V3{0.0f, 0.0f, 1.0f};
   }
   float s, c;
-  sincospif(q, &s, &c);
+  sincospi_small(q, &s, &c);
   const float r2 = r * r;
   const float k = r * fsqrt(2.0f - r2);
   return V3{k * c, k * s, 1.0f - r2};
@@ -193,9 +221,9 @@ __device__ __forceinline__ float brdf_pdf_only(const Pixel &px, V3 wi) {
   const V3 h = V3{px.wo.x + wi.x, px.wo.y + wi.y, px.wo.z + wi.z};
   const float hh = dot3(h, h);
   const float den = fmaf(px.alpha2, h.z * h.z, fmaf(h.x, h.x, h.y * h.y));
-  const float D = px.alpha2 * kInvPi * (hh / den) * (hh / den);
-  const float pggx = D * h.z / (4.0f * dot3(px.wo, h));
-  return fmaf(px.s_d * kInvPi, wi.z, (1.0f - px.s_d) * pggx);
+  const float R = frcp(den * den * dot3(px.wo, h));
+  const float pggx = 0.25f * px.a2_pi * hh * hh * h.z * R;
+  return fmaf(px.s_d_pi, wi.z, (1.0f - px.s_d) * pggx);
 }
 
 // ---------------------------------------------------------------------------

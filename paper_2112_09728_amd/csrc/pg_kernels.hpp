@@ -156,15 +156,16 @@ __device__ __forceinline__ void sample_pixel(const ParamsK &P, const ViewK &v, c
       const uint4 w4 = philox4x32_10(pix, P.frame, (uint32_t)s, P.view, P.key0, P.key1);
       const float zeta = u24(w4.x), xl = u24(w4.y), x1 = u24(w4.z), x2 = u24(w4.w);
       float sn, cs;
-      sincospif(2.0f * x2, &sn, &cs);
+      sincospi_small(2.0f * x2, &sn, &cs);
       if (zeta < pe) {
-        const float rho = fsqrt(-2.0f * logf(1.0f - x1));
+        // -2 ln(1 - x1) = -2 ln2 log2(1 - x1); 1 - x1 >= 2^-24 is normal
+        const float rho = fsqrt(-1.38629436f * __builtin_amdgcn_logf(1.0f - x1));
         const float z1 = rho * cs, z2 = rho * sn;
         const float ux = fmaf(G.l11, z1, G.mx);
         const float uy = fmaf(G.l22, z2, fmaf(G.l21, z1, G.my));
         if (ux >= 0.0f && ux <= 1.0f && uy >= 0.0f && uy <= 1.0f) {
           l = sq2hemi(ux, uy);
-          const float pg = G.norm * expf(-0.5f * fmaf(z1, z1, z2 * z2));
+          const float pg = G.norm * __builtin_amdgcn_exp2f(-0.72134752f * fmaf(z1, z1, z2 * z2));
           pb = l.z > 0.0f ? brdf_pdf_only(px, l) : 0.0f;
           D = fmaf(pe, pg, (1.0f - pe) * pb);
           code = 2;
@@ -191,8 +192,7 @@ __device__ __forceinline__ void sample_pixel(const ParamsK &P, const ViewK &v, c
             // GGX density of the drawn normal in closed form of xi_1:
             // D(h) = (1 - xi_1 (1 - alpha^2))^2 / (pi alpha^2)
             const float q = fmaf(-x1, 1.0f - px.alpha2, 1.0f);
-            const float Dh = q * q / (kPi * px.alpha2);
-            const float pggx = Dh * ch / (4.0f * woh);
+            const float pggx = 0.25f * kInvPi * q * q * ch * frcp(px.alpha2 * woh);
             pb = fmaf(px.s_d * kInvPi, l.z, (1.0f - px.s_d) * pggx);
           }
         }
@@ -201,7 +201,7 @@ __device__ __forceinline__ void sample_pixel(const ParamsK &P, const ViewK &v, c
           if (pe > 0.0f) {
             float ux, uy;
             hemi2sq(l, ux, uy);
-            pg = gauss_pdf_acc(G, ux, uy);
+            pg = gauss_pdf_fast(G, ux, uy);
           }
           D = fmaf(pe, pg, (1.0f - pe) * pb);
           code = 1;
@@ -373,21 +373,37 @@ __device__ __forceinline__ void stage_records(const ViewK &v, const SamplesK &S,
   constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH;
   const int plane = v.H * v.pitch;
   const int splane = S.spp * plane;
-  const int n = S.spp * SA;
-  for (int e = threadIdx.x; e < n; e += TW * TH) {
-    const int s = e / SA;
-    const int r = e - s * SA;
-    const int sy = r / SW, sx = r - sy * SW;
+  for (int e = threadIdx.x; e < SA; e += TW * TH) {
+    // e < 2^13, so the float quotient floors exactly
+    const int sy = (int)(((float)e + 0.5f) * (1.0f / SW));
+    const int sx = e - sy * SW;
     const int gx = tx0 - kR + sx, gy = ty0 - kR + sy;
-    float4 rec = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (gx >= 0 && gy >= 0 && gx < v.W && gy < v.H) {
-      const int o = (s * v.H + gy) * v.pitch + gx;
-      if (S.strat[o] == 1) {
-        const float p = S.pb[o];
-        if (p > 0.0f) rec = make_float4(S.dir[o], S.dir[splane + o], S.dir[2 * splane + o], S.L[o] / p);
+    const bool in = gx >= 0 && gy >= 0 && gx < v.W && gy < v.H;
+    for (int s = 0; s < S.spp; ++s) {
+      float4 rec = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (in) {
+        const int o = (s * v.H + gy) * v.pitch + gx;
+        if (S.strat[o] == 1) {
+          // a BRDF sample's density is a normal number (at least s_d cos/pi
+          // of a valid draw, or the GGX density of the drawn normal)
+          const float p = S.pb[o];
+          if (p > 0.0f)
+            rec = make_float4(S.dir[o], S.dir[splane + o], S.dir[2 * splane + o],
+                              S.L[o] * frcp(fmaxf(p, 1.17549435e-38f)));
+        }
       }
+      lds[s * SA + e] = rec;
     }
-    lds[e] = rec;
+  }
+}
+
+// LDS offset of each of the 49 positions of the pick window relative to the
+// pixel (position 24, the centre, is never used).
+template <int SW>
+__device__ __forceinline__ void fill_pick_offsets(short *off) {
+  if (threadIdx.x < kSide * kSide) {
+    const int o = threadIdx.x;
+    off[o] = (short)((o / kSide - kR) * SW + (o % kSide - kR));
   }
 }
 
@@ -436,20 +452,21 @@ __device__ __forceinline__ void em_visit(const EmCtx &c, float4 r, Accum &a) {
   }
 }
 
-// Pick m of pixel (x, y): 16-bit field of a stream-1 Philox word -> (offset,
-// sample) uniform over the 48 neighbours times spp.  Returns the LDS index.
-template <int SW, int SA>
-__device__ __forceinline__ int pick_index(uint4 w4, int m, int spp, uint32_t cs, uint32_t inv_spp, int lx,
-                                          int ly) {
+// Pick m of a pixel: the 16-bit field m of the stream-1 Philox words gives a
+// code c uniform over (48 neighbours) x spp; returns the LDS index of that
+// candidate.  All products fit 24 bits (full-rate v_mul_u32_u24); the code is
+// split as c = o spp + s by (c ceil(2^16/spp)) >> 16, exact for c < 48 spp.
+template <int SA>
+__device__ __forceinline__ int pick_entry(uint4 w4, int m, uint32_t cs, uint32_t inv_spp, uint32_t spp,
+                                          int own, const short *off) {
   const int wsel = (m >> 1) & 3;
   const uint32_t word = wsel == 0 ? w4.x : wsel == 1 ? w4.y : wsel == 2 ? w4.z : w4.w;
   const uint32_t h = (m & 1) ? (word >> 16) : (word & 0xFFFFu);
-  const uint32_t c = (h * cs) >> 16;                  // [0, 48 spp)
-  const uint32_t o0 = (c * inv_spp) >> 16;            // c / spp (exact for c < 48 spp <= 384)
-  const int s = (int)(c - o0 * (uint32_t)spp);
-  const int o = (int)o0 + (o0 >= (uint32_t)(kCand / 2) ? 1 : 0);
-  const int dy = o / kSide - kR, dx = o - (o / kSide) * kSide - kR;
-  return s * SA + (ly + kR + dy) * SW + (lx + kR + dx);
+  const uint32_t c = __umul24(h, cs) >> 16;
+  const uint32_t o0 = __umul24(c, inv_spp) >> 16;
+  const uint32_t s = c - __umul24(o0, spp);
+  const uint32_t o = o0 + (o0 >= (uint32_t)(kCand / 2) ? 1u : 0u);
+  return (int)__umul24(s, (uint32_t)SA) + own + off[o];
 }
 
 // Training list of one pixel: the LDS indices of its kept candidates, in the
@@ -457,8 +474,9 @@ __device__ __forceinline__ int pick_index(uint4 w4, int m, int spp, uint32_t cs,
 // index).  A candidate is kept when its staged record is a BRDF-strategy
 // sample inside the image.  Returns the list length.
 template <int TW, int TH>
-__device__ __forceinline__ int build_list(const ParamsK &P, const float4 *lds, uint16_t *list, int lane,
-                                          int lx, int ly, int k, int spp, uint32_t pix) {
+__device__ __forceinline__ int build_list(const ParamsK &P, const float4 *lds, const short *off,
+                                          uint16_t *list, int lane, int lx, int ly, int k, int spp,
+                                          uint32_t pix) {
   constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH, NT = TW * TH;
   k = k < 0 ? 0 : (k > P.k_max ? P.k_max : k);
   const int npick = 5 + (15 * (P.k_max - k)) / P.k_max;
@@ -473,7 +491,7 @@ __device__ __forceinline__ int build_list(const ParamsK &P, const float4 *lds, u
   uint4 w4 = make_uint4(0, 0, 0, 0);
   for (int m = 0; m < npick; ++m) {
     if ((m & 7) == 0) w4 = philox4x32_10(pix, P.frame, (1u << 16) | (uint32_t)(m >> 3), P.view, P.key0, P.key1);
-    const int e = pick_index<SW, SA>(w4, m, spp, cs, inv_spp, lx, ly);
+    const int e = pick_entry<SA>(w4, m, cs, inv_spp, (uint32_t)spp, own, off);
     if (lds[e].w != 0.0f) list[(n++) * NT + lane] = (uint16_t)e;
   }
   return n;
@@ -513,10 +531,12 @@ __global__ __launch_bounds__(TW *TH) void k_em(ParamsK P, ViewK v, SamplesK S, T
   extern __shared__ float4 lds[];  // records [spp][SH][SW], then lists [spp + 20][NT]
   __shared__ int s_cnt[kMaxLen];
   __shared__ int s_perm[NT];
+  __shared__ short s_off[kSide * kSide];
   uint16_t *list = reinterpret_cast<uint16_t *>(lds + S.spp * SA);
   const int tile = xcd_tile(blockIdx.x, n_tiles);
   const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
   stage_records<TW, TH>(v, S, lds, tx0, ty0);
+  fill_pick_offsets<SW>(s_off);
   const int plane = v.H * v.pitch;
   // natural pixel order: the number of candidates of this lane's pixel
   // (0 when it is not trained)
@@ -548,7 +568,7 @@ __global__ __launch_bounds__(TW *TH) void k_em(ParamsK P, ViewK v, SamplesK S, T
   const float rough = v.rough[idx];
   if (!(dot3(n, o) > 0.0f && rough >= P.rough_min)) return;
   // training list of this pixel, kept in this lane's column of the list area
-  const int len = build_list<TW, TH>(P, lds, list, threadIdx.x, lx, ly, (int)g[7], S.spp,
+  const int len = build_list<TW, TH>(P, lds, s_off, list, threadIdx.x, lx, ly, (int)g[7], S.spp,
                                      (uint32_t)(y * v.W + x));
   if (len == 0) return;  // no training sample: the model stays as it is
   EmCtx c;
@@ -564,7 +584,7 @@ __global__ __launch_bounds__(TW *TH) void k_em(ParamsK P, ViewK v, SamplesK S, T
     if (!batch) {
       // stepwise merge with eta = 1/(k+1) and evidence W; only ratios of
       // evidences appear, so a subnormal B1 is harmless
-      const float eta = 1.0f / (g[7] + 1.0f);
+      const float eta = frcp(g[7] + 1.0f);  // k + 1 in [1, kMax + 1]
       const float sw = fmaf(1.0f - eta, g[6], eta * a.B0);
       const float so = (1.0f - eta) * g[5] * g[6];
       const float sn = eta * a.B1;
@@ -641,10 +661,12 @@ __global__ __launch_bounds__(TW *TH) void k_nll(ParamsK P, ViewK v, SamplesK S, 
                                                 const float *__restrict__ grad_out, float *__restrict__ grad,
                                                 float *__restrict__ nll, int tiles_x, int n_tiles) {
   extern __shared__ float4 lds[];
+  __shared__ short s_off[kSide * kSide];
   constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH;
   const int tile = xcd_tile(blockIdx.x, n_tiles);
   const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
   stage_records<TW, TH>(v, S, lds, tx0, ty0);
+  fill_pick_offsets<SW>(s_off);
   __syncthreads();
   const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
   const int x = tx0 + lx, y = ty0 + ly;
@@ -685,7 +707,7 @@ __global__ __launch_bounds__(TW *TH) void k_nll(ParamsK P, ViewK v, SamplesK S, 
     uint4 w4 = make_uint4(0, 0, 0, 0);
     for (int m = 0; m < npick; ++m) {
       if ((m & 7) == 0) w4 = philox4x32_10(pix, P.frame, (1u << 16) | (uint32_t)(m >> 3), P.view, P.key0, P.key1);
-      nll_visit(c, lds[pick_index<SW, SA>(w4, m, S.spp, cs, inv_spp, lx, ly)], a);
+      nll_visit(c, lds[pick_entry<SA>(w4, m, cs, inv_spp, (uint32_t)S.spp, own, s_off)], a);
     }
     const float sc = grad_out ? grad_out[idx] : 1.0f;
     gr[0] = sc * a.gmx;
