@@ -60,6 +60,9 @@ def parse():
                     help="budget of the oracle timing on the host (0 = skip)")
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--tile", default=None, help="training tile WxH (default: the library's)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run one untimed device-to-device copy of MIB MiB (a reference "
+                         "for the FETCH_SIZE/WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -123,6 +126,14 @@ def main():
     for t in range(a.warmup):
         frame(t)
     torch.cuda.synchronize()
+    if a.copy_calibration > 0:
+        n = a.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(a.steps)]
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()

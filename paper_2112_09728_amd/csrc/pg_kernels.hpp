@@ -500,7 +500,9 @@ __device__ __forceinline__ int build_list(const ParamsK &P, const float4 *lds, c
 // Order the tile's pixels by decreasing work `len` (0 .. kMaxLen - 1) so that
 // the lanes of a wave carry nearly equal work (the order inside a class is
 // irrelevant: a pixel's arithmetic does not depend on the lane it runs on).
-// Returns the tile-local pixel index this lane works on.
+// The k-th heaviest group of 64 pixels goes to wave (k + block) mod waves,
+// so that the heavy waves of the blocks resident on a CU do not all land on
+// the same SIMD.  Returns the tile-local pixel index this lane works on.
 constexpr int kMaxLen = kMaxSpp + 21;
 
 template <int NT>
@@ -519,7 +521,10 @@ __device__ __forceinline__ int balance(int len, int *cnt, int *perm) {
     }
   }
   __syncthreads();
-  perm[cnt[len] + rank] = t;
+  constexpr int NW = NT / 64;
+  const int pos = cnt[len] + rank;                                // rank in the sorted order
+  const int wave = NW > 1 ? ((pos >> 6) + (int)blockIdx.x) % NW : 0;
+  perm[wave * 64 + (pos & 63)] = t;
   __syncthreads();
   return perm[t];
 }
