@@ -60,6 +60,10 @@ def parse():
                     help="budget of the oracle timing on the host (0 = skip)")
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--tile", default=None, help="training tile WxH (default: the library's)")
+    ap.add_argument("--workload", default="1080p", choices=["1080p", "batched16"],
+                    help="1080p: the single-view path (default); batched16: 16 uneven views, "
+                         "FP16 Gamma, batched frame (eager and graph-replayed) against 16 plain "
+                         "per-view launch sequences")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one untimed device-to-device copy of MIB MiB (a reference "
                          "for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -78,6 +82,8 @@ def main():
     from paper_2112_09728_amd import workload as wl
 
     pg.lib()  # fail loudly without the HIP library
+    if a.workload == "batched16":
+        return bench_batched(a)
     cfg = wl.CONFIGS["1080p_spp1_64f_fp32_pan"]
     seed = cfg["seed"] if a.seed is None else a.seed
     W, H, S = a.width, a.height, a.spp
@@ -207,6 +213,110 @@ def main():
             "light_field_us": round(float(lf.mean()) * 1e3, 2),
         },
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(a):
+    """16 views of uneven size and spp, FP16 Gamma: Mpix/s over all views of
+    the batched frame (eager, and replayed from captured graphs) against 16
+    plain per-view launch sequences (reproject+sample, light field, EM) on the
+    same frames.  The light field is part of every variant here (the batched
+    frame fuses it into its sampling launch)."""
+    import torch
+
+    import paper_2112_09728_amd as pg
+    from paper_2112_09728_amd import workload as wl
+
+    cfg = wl.CONFIGS["batched_16_views"]
+    seed = cfg["seed"] if a.seed is None else a.seed
+    vs = wl.batched_views(cfg["n_views"], cfg["sizes"], cfg["spp_range"], seed)
+    warm, steps = min(a.warmup, 4), min(a.steps, 12)
+    frames_n = warm + steps
+    t0 = time.time()
+    seqs = [wl.Sequence(w, h, sd) for (w, h, _, sd) in vs]
+    specs = []
+    dev = []  # dev[t][i] = DeviceFrame
+    for t in range(frames_n):
+        row = []
+        for i, seq in enumerate(seqs):
+            fr = seq.frame(t)
+            if t == 0:
+                w, h, spp, sd = vs[i]
+                specs.append(dict(width=w, height=h, spp=spp, seed=sd, lights=fr["lights"],
+                                  ambient=float(fr["ambient"]), view=i))
+            row.append(pg.DeviceFrame(fr))
+        dev.append(row)
+        print(f"bench: batched frame {t} uploaded ({time.time() - t0:.0f} s)", file=sys.stderr, flush=True)
+    px = sum(w * h for (w, h, _, _) in vs)
+    samples = sum(w * h * spp for (w, h, spp, _) in vs)
+
+    def pairs(t):
+        return [(dev[t][i], dev[t - 1][i] if t else None) for i in range(len(vs))]
+
+    def timed(run):
+        for t in range(warm):
+            run(t)
+        torch.cuda.synchronize()
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record()
+        for t in range(warm, frames_n):
+            run(t)
+        s1.record()
+        torch.cuda.synchronize()
+        return s0.elapsed_time(s1) / steps
+
+    plain = [pg.Guide(s["width"], s["height"], s["lights"], s["ambient"], spp=s["spp"], seed=s["seed"],
+                      view_id=s["view"], gamma_dtype=torch.float16) for s in specs]
+
+    def run_plain(t):
+        for i, g in enumerate(plain):
+            g.step(dev[t][i], dev[t - 1][i] if t else None, frame=t)
+
+    ms_plain = timed(run_plain)
+    bg = pg.BatchedGuide(specs, gamma_dtype=torch.float16)
+    tune = bg.autotune(pairs(0), 0, reps=2)
+    bg = pg.BatchedGuide(specs, gamma_dtype=torch.float16, tile=bg.tile)
+    ms_eager = timed(lambda t: bg.step(pairs(t), t))
+    same = all(torch.equal(bg.state(i).view(torch.int16), plain[i].state.view(torch.int16))
+               for i in range(len(vs)))
+    bgg = pg.BatchedGuide(specs, gamma_dtype=torch.float16, tile=bg.tile)
+    ms_graph = timed(lambda t: bgg.step(pairs(t), t, graph=True))
+    same = same and all(torch.equal(bgg.state(i).view(torch.int16), plain[i].state.view(torch.int16))
+                        for i in range(len(vs)))
+    print(f"bench: batched16 plain {ms_plain:.3f} ms, batched eager {ms_eager:.3f} ms, graph {ms_graph:.3f} ms; "
+          f"tile {bg.tile}; autotuner {tune}", file=sys.stderr, flush=True)
+    G = 16
+    bytes_px = sum(w * h * (bytes_reproject_sample(G, spp) + 1 + 4 * spp + bytes_em(G, spp))
+                   for (w, h, spp, _) in vs)
+    gbs = bytes_px / (ms_graph * 1e-3) / 1e9
+    out = {
+        "metric": "total Mpix/s over 16 views, batched frame vs 16 plain launch sequences",
+        "value": round(px / (ms_graph * 1e-3) / 1e6, 2),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": round(ms_graph, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"16 views ({px / 1e6:.1f} Mpx, {samples / 1e6:.0f} M samples per frame), "
+                        f"camera-pan sequences, Gamma f16, graph-replayed batched frame",
+            "views": [f"{w}x{h} spp{spp}" for (w, h, spp, _) in vs],
+            "tile": list(bg.tile),
+        },
+        "plain_ms_per_step": round(ms_plain, 4),
+        "batched_eager_ms_per_step": round(ms_eager, 4),
+        "speedup_vs_plain": round(ms_plain / ms_graph, 3),
+        "identical_to_plain": bool(same),
+        "roofline": {"bound": "hbm", "kernel": "k_rs_batched + k_em_batched", "achieved": round(gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 

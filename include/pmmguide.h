@@ -46,6 +46,7 @@
  */
 #ifndef PMMGUIDE_H
 #define PMMGUIDE_H
+#include <stddef.h>
 #include <stdint.h>
 #ifdef __cplusplus
 extern "C" {
@@ -207,6 +208,49 @@ pg_status pg_em_update(const pg_params *p, const pg_view *v, const pg_samples *i
 pg_status pg_nll_backward(const pg_params *p, const pg_view *v, const pg_samples *in,
                           const float *theta, const float *grad_out, float *grad_theta,
                           float *nll, void *stream);
+
+/* ---- Batched frame: many views in two persistent launches ----------------
+ * One frame of n views of any size and spp (Sec. 3.1 and Sec. 3.2 for each
+ * view, with the light-field stand-in between them) as an upload of a packed
+ * table followed by two persistent launches over the tiles of all views:
+ * reprojection + guided sampling + light field, then the online EM update.
+ * Per view the results are bit-identical to pg_reproject_sample,
+ * pg_light_field and pg_em_update called with that view's arguments and the
+ * same training tile. */
+typedef struct pg_batch_view {
+  pg_params params;    /* seed, frame and view may differ between views; every
+                          other field must equal view 0's (tile_w/tile_h of
+                          view 0 pick the training tile, 0 = default)        */
+  pg_view cur;         /* this frame's G-buffer (albedo required)             */
+  pg_view prev;        /* previous frame's (read when params.frame > 0)       */
+  pg_gamma gamma_in;   /* previous state (read when params.frame > 0)         */
+  pg_gamma gamma_out;  /* this frame's state, cur's height and pitch; must not
+                          alias gamma_in; one dtype for all views             */
+  pg_samples samples;  /* records; radiance is written too                    */
+  const uint8_t *vis;  /* [H*pitch] light visibility bits (device)            */
+  pg_lights lights;    /* this view's light field                             */
+} pg_batch_view;
+
+/* Bytes of the packed table for n_views views (0 for n_views < 1). */
+size_t pg_batch_table_bytes(int32_t n_views);
+
+/* Checks n_views views (the same checks as the single-view calls, plus a
+ * common dtype and shared parameters) and writes the packed table into
+ * host_table (caller-owned host memory of at least pg_batch_table_bytes
+ * bytes).  Host only: no GPU work, nothing retained. */
+pg_status pg_batch_pack(const pg_batch_view *views, int32_t n_views, void *host_table, size_t bytes);
+
+/* Enqueues on `stream`: a copy of `bytes` bytes from host_table to
+ * device_table (caller-owned device memory), then the two persistent
+ * launches, which read the table there.  The launch configuration (dtype,
+ * training tile, largest spp) is read from host_table during the call.
+ * host_table should be pinned (hipHostMalloc) so that the copy is
+ * asynchronous and can be captured; it must not be re-packed before the copy
+ * has run.  A captured graph replays re-packed tables of other frames and
+ * views as long as dtype, tile and largest spp stay those of the capture (a
+ * table that differs in them is skipped by the kernels: nothing is written).
+ * Views must not share output buffers. */
+pg_status pg_frame_batched(const void *host_table, void *device_table, size_t bytes, void *stream);
 
 /* Diagnostic: Philox4x32-10 (Salmon et al., SC 2011), the generator behind
  * every random draw above, for n counters: counters [n][4] uint32 and out

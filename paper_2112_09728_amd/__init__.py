@@ -57,8 +57,15 @@ class PgLights(C.Structure):
                 ("light", (C.c_float * 5) * MAX_LIGHTS)]
 
 
+class PgBatchView(C.Structure):
+    _fields_ = [("params", PgParams), ("cur", PgView), ("prev", PgView), ("gamma_in", PgGamma),
+                ("gamma_out", PgGamma), ("samples", PgSamples), ("vis", C.c_void_p),
+                ("lights", PgLights)]
+
+
 EXPORTS = ("pg_params_default", "pg_reproject", "pg_sample_mis", "pg_reproject_sample", "pg_pdf",
-           "pg_light_field", "pg_em_update", "pg_nll_backward", "pg_philox", "pg_last_error")
+           "pg_light_field", "pg_em_update", "pg_nll_backward", "pg_batch_table_bytes",
+           "pg_batch_pack", "pg_frame_batched", "pg_philox", "pg_last_error")
 
 _lib = None
 
@@ -84,10 +91,14 @@ def lib():
         L.pg_light_field.argtypes = [P, P, P, P, P]
         L.pg_em_update.argtypes = [P, P, P, PgGamma, C.c_int32, P]
         L.pg_nll_backward.argtypes = [P, P, P, P, P, P, P, P]
+        L.pg_batch_table_bytes.argtypes = [C.c_int32]
+        L.pg_batch_pack.argtypes = [P, C.c_int32, P, C.c_size_t]
+        L.pg_frame_batched.argtypes = [P, P, C.c_size_t, P]
         L.pg_philox.argtypes = [C.c_int32, P, C.c_uint64, P, P]
         L.pg_last_error.restype = C.c_char_p
         for name in EXPORTS[:-1]:
             getattr(L, name).restype = C.c_int
+        L.pg_batch_table_bytes.restype = C.c_size_t
         _lib = L
     return _lib
 
@@ -285,6 +296,29 @@ def nll_backward(p: PgParams, view: View, samples: Samples, theta, grad_out=None
     return nll, grad
 
 
+def batch_table_bytes(n_views: int) -> int:
+    return int(lib().pg_batch_table_bytes(n_views))
+
+
+def batch_pack(views, host_table) -> None:
+    """Pack a sequence of PgBatchView into host_table (a uint8 CPU tensor,
+    pinned for graph capture)."""
+    if host_table.is_cuda or not host_table.is_contiguous():
+        raise ValueError("host_table must be a contiguous host tensor")
+    arr = (PgBatchView * len(views))(*views)
+    _check(lib().pg_batch_pack(arr, len(views), C.c_void_p(host_table.data_ptr()),
+                               host_table.numel() * host_table.element_size()), "pg_batch_pack")
+
+
+def frame_batched(host_table, device_table) -> None:
+    """Upload the packed table and run the batched frame on the current stream."""
+    _require(device_table, None, "device_table")
+    n = min(host_table.numel() * host_table.element_size(),
+            device_table.numel() * device_table.element_size())
+    _check(lib().pg_frame_batched(C.c_void_p(host_table.data_ptr()), _ptr(device_table), n,
+                                  _stream()), "pg_frame_batched")
+
+
 def philox(counters, seed: int):
     """Philox4x32-10 words for device counters [n][4] (int32 tensor holding uint32 bits)."""
     import torch
@@ -295,4 +329,4 @@ def philox(counters, seed: int):
     return out
 
 
-from .guide import DeviceFrame, Guide, NLLFunction  # noqa: E402  (needs the names above)
+from .guide import BatchedGuide, DeviceFrame, Guide, NLLFunction  # noqa: E402  (needs the names above)

@@ -129,12 +129,34 @@ __device__ __forceinline__ int reproject_pixel(const ParamsK &P, const ViewK &cu
   return qy * prev.W + qx;
 }
 
+// Analytic incident radiance (stand-in for the trace).  For unit w and xi,
+// w . xi - 1 = -|w - xi|^2 / 2, which has no cancellation near the axis.
+struct LightsK {
+  int count;
+  float ambient;
+  float l[8][5];
+};
+
+__device__ __forceinline__ float light_radiance(const LightsK &Lt, uint32_t bits, V3 wdir) {
+  const V3 w = normalized(wdir);
+  float L = Lt.ambient;
+  for (int k = 0; k < Lt.count; ++k) {
+    if (!((bits >> k) & 1u)) continue;
+    const V3 a = V3{w.x - Lt.l[k][0], w.y - Lt.l[k][1], w.z - Lt.l[k][2]};
+    L = fmaf(Lt.l[k][4], expf(-0.5f * Lt.l[k][3] * dot3(a, a)), L);
+  }
+  return L;
+}
+
 // ---------------------------------------------------------------------------
 // Sampling of one pixel (Sec. 3.1, Eq. (2)).  Each strategy's own density is
 // taken in its sample space (Gaussian from z, GGX from xi_1), the other
 // component from the direction.
+// With Lt given, the radiance of each sample is evaluated as well (the
+// batched frame fuses the trace stand-in into this pass).
 __device__ __forceinline__ void sample_pixel(const ParamsK &P, const ViewK &v, const SamplesK &S,
-                                             int x, int y, const float g[8]) {
+                                             int x, int y, const float g[8], const LightsK *Lt = nullptr,
+                                             uint32_t visbits = 0) {
   const int plane = v.H * v.pitch;
   const int idx = y * v.pitch + x;
   const int splane = S.spp * plane;
@@ -223,6 +245,7 @@ __device__ __forceinline__ void sample_pixel(const ParamsK &P, const ViewK &v, c
     S.pmix[rec] = D;
     S.pb[rec] = pb;
     S.strat[rec] = code;
+    if (Lt) S.L[rec] = (code == 1 || code == 2) ? light_radiance(*Lt, visbits, w) : 0.0f;
   }
 }
 
@@ -317,13 +340,6 @@ __global__ __launch_bounds__(256) void k_pdf(ParamsK P, ViewK v, const TG *__res
   }
 }
 
-// Analytic incident radiance (stand-in for the trace).  For unit w and xi,
-// w . xi - 1 = -|w - xi|^2 / 2, which has no cancellation near the axis.
-struct LightsK {
-  int count;
-  float ambient;
-  float l[8][5];
-};
 
 __global__ __launch_bounds__(256) void k_light(LightsK Lt, ViewK v, const uint8_t *__restrict__ vis,
                                                SamplesK S) {
@@ -337,17 +353,9 @@ __global__ __launch_bounds__(256) void k_light(LightsK Lt, ViewK v, const uint8_
   for (int s = 0; s < S.spp; ++s) {
     const int r = (s * v.H + y) * v.pitch + x;
     const uint8_t code = S.strat[r];
-    float L = 0.0f;
-    if (code == 1 || code == 2) {
-      const V3 w = normalized(V3{S.dir[r], S.dir[splane + r], S.dir[2 * splane + r]});
-      L = Lt.ambient;
-      for (int k = 0; k < Lt.count; ++k) {
-        if (!((bits >> k) & 1u)) continue;
-        const V3 a = V3{w.x - Lt.l[k][0], w.y - Lt.l[k][1], w.z - Lt.l[k][2]};
-        L = fmaf(Lt.l[k][4], expf(-0.5f * Lt.l[k][3] * dot3(a, a)), L);
-      }
-    }
-    S.L[r] = L;
+    S.L[r] = (code == 1 || code == 2)
+                 ? light_radiance(Lt, bits, V3{S.dir[r], S.dir[splane + r], S.dir[2 * splane + r]})
+                 : 0.0f;
   }
 }
 
@@ -506,7 +514,7 @@ __device__ __forceinline__ int build_list(const ParamsK &P, const float4 *lds, c
 constexpr int kMaxLen = kMaxSpp + 21;
 
 template <int NT>
-__device__ __forceinline__ int balance(int len, int *cnt, int *perm) {
+__device__ __forceinline__ int balance(int len, int *cnt, int *perm, int rot) {
   const int t = threadIdx.x;
   if (t < kMaxLen) cnt[t] = 0;
   __syncthreads();
@@ -523,25 +531,32 @@ __device__ __forceinline__ int balance(int len, int *cnt, int *perm) {
   __syncthreads();
   constexpr int NW = NT / 64;
   const int pos = cnt[len] + rank;                                // rank in the sorted order
-  const int wave = NW > 1 ? ((pos >> 6) + (int)blockIdx.x) % NW : 0;
+  const int wave = NW > 1 ? ((pos >> 6) + rot) % NW : 0;
   perm[wave * 64 + (pos & 63)] = t;
   __syncthreads();
   return perm[t];
 }
 
+// LDS of one training tile besides the dynamic records/lists area.
+template <int NT>
+struct EmShared {
+  int cnt[kMaxLen];
+  int perm[NT];
+  short off[kSide * kSide];
+};
+
+// One training tile: stage the records of the tile and its halo, sort the
+// pixels by candidate count, build each pixel's training list and run the
+// E- and M-steps.  Every thread of the block calls it (it synchronises); no
+// thread returns early, so a persistent block can loop over tiles.
 template <typename TG, int TW, int TH>
-__global__ __launch_bounds__(TW *TH) void k_em(ParamsK P, ViewK v, SamplesK S, TG *__restrict__ gamma,
-                                               int iterations, int batch, int tiles_x, int n_tiles) {
+__device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const SamplesK &S, TG *gamma,
+                                        int iterations, int batch, int tx0, int ty0, int rot,
+                                        float4 *lds, EmShared<TW * TH> &sh) {
   constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH, NT = TW * TH;
-  extern __shared__ float4 lds[];  // records [spp][SH][SW], then lists [spp + 20][NT]
-  __shared__ int s_cnt[kMaxLen];
-  __shared__ int s_perm[NT];
-  __shared__ short s_off[kSide * kSide];
   uint16_t *list = reinterpret_cast<uint16_t *>(lds + S.spp * SA);
-  const int tile = xcd_tile(blockIdx.x, n_tiles);
-  const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
   stage_records<TW, TH>(v, S, lds, tx0, ty0);
-  fill_pick_offsets<SW>(s_off);
+  fill_pick_offsets<SW>(sh.off);
   const int plane = v.H * v.pitch;
   // natural pixel order: the number of candidates of this lane's pixel
   // (0 when it is not trained)
@@ -562,20 +577,27 @@ __global__ __launch_bounds__(TW *TH) void k_em(ParamsK P, ViewK v, SamplesK S, T
   }
   // pixels by decreasing candidate count; the barriers inside also publish
   // the staged records
-  const int me = balance<NT>(ncand, s_cnt, s_perm);
+  const int me = balance<NT>(ncand, sh.cnt, sh.perm, rot);
   const int lx = me % TW, ly = me / TW;
   const int x = tx0 + lx, y = ty0 + ly;
-  if (x >= v.W || y >= v.H) return;
   const int idx = y * v.pitch + x;
+  bool active = x < v.W && y < v.H;
   float g[8];
-  gamma_load(gamma, plane, idx, g);
-  const V3 n = load3(v.n, plane, idx), o = load3(v.o, plane, idx);
-  const float rough = v.rough[idx];
-  if (!(dot3(n, o) > 0.0f && rough >= P.rough_min)) return;
+  V3 n = V3{0, 0, 0}, o = V3{0, 0, 0};
+  float rough = 0.0f;
+  if (active) {
+    gamma_load(gamma, plane, idx, g);
+    n = load3(v.n, plane, idx);
+    o = load3(v.o, plane, idx);
+    rough = v.rough[idx];
+    active = dot3(n, o) > 0.0f && rough >= P.rough_min;
+  }
   // training list of this pixel, kept in this lane's column of the list area
-  const int len = build_list<TW, TH>(P, lds, s_off, list, threadIdx.x, lx, ly, (int)g[7], S.spp,
-                                     (uint32_t)(y * v.W + x));
-  if (len == 0) return;  // no training sample: the model stays as it is
+  int len = 0;
+  if (active)
+    len = build_list<TW, TH>(P, lds, sh.off, list, threadIdx.x, lx, ly, (int)g[7], S.spp,
+                             (uint32_t)(y * v.W + x));
+  if (len == 0) return;  // no training sample (or no pixel): the model stays as it is
   EmCtx c;
   c.px = make_pixel(P, n, o, rough, v.alb[idx]);
   const int iters = batch ? iterations : 1;
@@ -623,6 +645,16 @@ __global__ __launch_bounds__(TW *TH) void k_em(ParamsK P, ViewK v, SamplesK S, T
     }
   }
   gamma_store(gamma, plane, idx, g);
+}
+
+template <typename TG, int TW, int TH>
+__global__ __launch_bounds__(TW *TH) void k_em(ParamsK P, ViewK v, SamplesK S, TG *__restrict__ gamma,
+                                               int iterations, int batch, int tiles_x, int n_tiles) {
+  extern __shared__ float4 lds[];  // records [spp][SH][SW], then lists [spp + 20][NT]
+  __shared__ EmShared<TW * TH> sh;
+  const int tile = xcd_tile(blockIdx.x, n_tiles);
+  em_tile<TG, TW, TH>(P, v, S, gamma, iterations, batch, (tile % tiles_x) * TW, (tile / tiles_x) * TH,
+                      (int)blockIdx.x, lds, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -727,6 +759,118 @@ __global__ __launch_bounds__(TW *TH) void k_nll(ParamsK P, ViewK v, SamplesK S, 
     for (int ch = 0; ch < 8; ++ch) grad[ch * plane + idx] = gr[ch];
   }
   if (nll) nll[idx] = a.loss;
+}
+
+// ---------------------------------------------------------------------------
+// Batched frame: many views of any size and spp in two persistent launches
+// (reprojection + sampling + light, then training) that read everything from
+// a table in device memory, so that one captured graph (table upload + two
+// kernels) replays later frames of all views once the table is re-packed.
+struct BatchViewK {
+  ViewK cur;
+  const float *prev_n, *prev_z;
+  const void *gprev;
+  void *gout;
+  SamplesK S;
+  const uint8_t *vis;
+  LightsK lights;
+  uint32_t key0, key1, frame, view;
+  int rs_begin, rs_tiles_x, em_begin, em_tiles_x;
+};
+
+struct BatchHeader {
+  int n_views, rs_tiles, em_tiles, dtype, max_spp, tile_w, tile_h, pad;
+  ParamsK base;  // fields shared by every view (key, frame, view come per view)
+};
+
+constexpr int kBatchViewsOffset = (int)((sizeof(BatchHeader) + 63) / 64 * 64);
+
+__device__ __forceinline__ const BatchViewK *batch_views(const char *table) {
+  return reinterpret_cast<const BatchViewK *>(table + kBatchViewsOffset);
+}
+
+// The view owning tile t: the last one whose first tile is <= t (the tiles of
+// consecutive views are contiguous).  Uniform across the block.
+template <bool EM>
+__device__ __forceinline__ int batch_find(const BatchViewK *vs, int n, int t) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int b = EM ? vs[mid].em_begin : vs[mid].rs_begin;
+    if (b <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ ParamsK batch_params(const ParamsK &base, const BatchViewK &bv) {
+  ParamsK P = base;
+  P.key0 = bv.key0;
+  P.key1 = bv.key1;
+  P.frame = bv.frame;
+  P.view = bv.view;
+  return P;
+}
+
+// Persistent reprojection + sampling + light field over the 64x4 pixel tiles
+// of all views, grid-stride.  `dtype` is the launch's Gamma type: a table of
+// another type is not processed.
+template <typename TG>
+__global__ __launch_bounds__(256) void k_rs_batched(const char *__restrict__ table, int dtype) {
+  const BatchHeader *hd = reinterpret_cast<const BatchHeader *>(table);
+  if (hd->dtype != dtype) return;
+  const int n_views = hd->n_views, n_tiles = hd->rs_tiles;
+  const BatchViewK *vs = batch_views(table);
+  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const BatchViewK &bv = vs[batch_find<false>(vs, n_views, t)];
+    const int local = t - bv.rs_begin;
+    const int x = (local % bv.rs_tiles_x) * 64 + (int)(threadIdx.x & 63);
+    const int y = (local / bv.rs_tiles_x) * 4 + (int)(threadIdx.x >> 6);
+    const ViewK cur = bv.cur;
+    if (x >= cur.W || y >= cur.H) continue;
+    const ParamsK P = batch_params(hd->base, bv);
+    ViewK prev = cur;
+    prev.n = bv.prev_n;
+    prev.z = bv.prev_z;
+    const bool has_prev = bv.frame > 0;
+    float g[8];
+    reproject_pixel(P, cur, prev, (const TG *)bv.gprev, has_prev, x, y, g);
+    const int idx = y * cur.pitch + x;
+    gamma_store((TG *)bv.gout, cur.H * cur.pitch, idx, g);
+    // sample from the state as stored
+    float gs[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      TG q;
+      GammaIO<TG>::store(&q, c == 6 ? fminf(g[c], GammaIO<TG>::kMax) : g[c]);
+      gs[c] = GammaIO<TG>::load(&q);
+    }
+    sample_pixel(P, cur, bv.S, x, y, gs, &bv.lights, bv.vis[idx]);
+  }
+}
+
+// Persistent training over the TW x TH tiles of all views.  The blocks on XCD
+// j (block ids j, j+8, ...) take the j-th eighth of the tile list in order,
+// so that neighbouring tiles share that XCD's L2.  `spp_cap` is the spp the
+// dynamic LDS was sized for: a table that needs more is not processed.
+template <typename TG, int TW, int TH>
+__global__ __launch_bounds__(TW *TH) void k_em_batched(const char *__restrict__ table, int dtype, int spp_cap) {
+  extern __shared__ float4 lds[];
+  __shared__ EmShared<TW * TH> sh;
+  const BatchHeader *hd = reinterpret_cast<const BatchHeader *>(table);
+  if (hd->dtype != dtype || hd->max_spp > spp_cap || hd->tile_w != TW || hd->tile_h != TH) return;
+  const int n_views = hd->n_views, n_tiles = hd->em_tiles;
+  const BatchViewK *vs = batch_views(table);
+  const int G = gridDim.x, xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int per = (G - xcd + 7) >> 3;  // blocks on this XCD
+  const int lo = (int)((long long)n_tiles * xcd / 8), hi = (int)((long long)n_tiles * (xcd + 1) / 8);
+  for (int t = lo + slot; t < hi; t += per) {
+    __syncthreads();  // the previous tile's LDS is no longer read
+    const BatchViewK &bv = vs[batch_find<true>(vs, n_views, t)];
+    const int l = t - bv.em_begin;
+    const ParamsK P = batch_params(hd->base, bv);
+    em_tile<TG, TW, TH>(P, bv.cur, bv.S, (TG *)bv.gout, 1, 0, (l % bv.em_tiles_x) * TW,
+                        (l / bv.em_tiles_x) * TH, t, lds, sh);
+  }
 }
 
 // Philox words for given counters (diagnostic entry).

@@ -5,7 +5,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <type_traits>
 
 #include "pg_kernels.hpp"
@@ -213,6 +216,125 @@ void launch_nll(Tile t, const ParamsK &P, const ViewK &v, const SamplesK &S, con
   else launch_nll_t<64, 2>(P, v, S, theta, go, grad, nll, st);
 }
 
+LightsK to_k(const pg_lights *l) {
+  LightsK L;
+  std::memset(&L, 0, sizeof(L));
+  L.count = l->count;
+  L.ambient = l->ambient;
+  for (int k = 0; k < l->count; ++k)
+    for (int c = 0; c < 5; ++c) L.l[k][c] = l->light[k][c];
+  return L;
+}
+
+pg_status check_lights(const pg_lights *l, const uint8_t *vis) {
+  if (!l) return fail(PG_ERR_ARG, "lights is NULL");
+  if (l->count < 0 || l->count > PG_MAX_LIGHTS) return fail(PG_ERR_ARG, "lights->count out of range");
+  if (!vis && l->count > 0) return fail(PG_ERR_ARG, "vis is NULL");
+  return PG_OK;
+}
+
+// ---- batched frame ----------------------------------------------------------
+constexpr int kBatchMagic = 0x31424750;  // "PGB1"
+
+size_t batch_bytes(int n) { return (size_t)kBatchViewsOffset + (size_t)n * sizeof(BatchViewK); }
+
+// Parameters every view of a batch must share (all but seed, frame, view).
+bool shared_params_equal(const pg_params &a, const pg_params &b) {
+  return a.k_max == b.k_max && a.radius == b.radius && a.pi_init == b.pi_init && a.pi_lo == b.pi_lo &&
+         a.pi_hi == b.pi_hi && a.eps_sigma == b.eps_sigma && a.tau_depth == b.tau_depth &&
+         a.tau_normal == b.tau_normal && a.rough_min == b.rough_min && a.s_diffuse == b.s_diffuse &&
+         a.f0 == b.f0 && a.flags == b.flags && a.tile_w == b.tile_w && a.tile_h == b.tile_h;
+}
+
+pg_status in_view(pg_status st, int i) {
+  if (st != PG_OK) g_last_error += " (view " + std::to_string(i) + ")";
+  return st;
+}
+
+pg_status check_batch_view(const pg_batch_view &b, int dtype) {
+  pg_status st;
+  if ((st = check_params(&b.params)) || (st = check_view(&b.cur, "cur", true)) ||
+      (st = check_gamma(b.gamma_out, "gamma_out")) || (st = check_samples(&b.samples, true, true)) ||
+      (st = check_lights(&b.lights, b.vis)))
+    return st;
+  if (b.params.flags & PG_EM_BATCH) return fail(PG_ERR_UNSUPPORTED, "the batched frame runs the online update only");
+  if (b.gamma_out.dtype != dtype) return fail(PG_ERR_ARG, "views store Gamma in different dtypes");
+  if (b.params.frame > 0) {
+    if ((st = check_view(&b.prev, "prev", false)) || (st = check_gamma(b.gamma_in, "gamma_in"))) return st;
+    if (b.gamma_in.dtype != dtype) return fail(PG_ERR_ARG, "gamma_in and gamma_out dtypes differ");
+    if (b.gamma_in.data == b.gamma_out.data) return fail(PG_ERR_ARG, "gamma_in aliases gamma_out");
+  }
+  return PG_OK;
+}
+
+BatchViewK to_batch(const pg_batch_view &b, int rs_begin, int em_begin, Tile t) {
+  BatchViewK k;
+  std::memset(&k, 0, sizeof(k));
+  k.cur = to_k(&b.cur);
+  const bool has_prev = b.params.frame > 0;
+  k.prev_n = has_prev ? b.prev.normal : nullptr;
+  k.prev_z = has_prev ? b.prev.depth : nullptr;
+  k.gprev = has_prev ? b.gamma_in.data : nullptr;
+  k.gout = b.gamma_out.data;
+  k.S = to_k(&b.samples);
+  k.vis = b.vis;
+  k.lights = to_k(&b.lights);
+  const ParamsK P = to_k(&b.params);
+  k.key0 = P.key0;
+  k.key1 = P.key1;
+  k.frame = P.frame;
+  k.view = P.view;
+  k.rs_begin = rs_begin;
+  k.rs_tiles_x = (b.cur.width + 63) / 64;
+  k.em_begin = em_begin;
+  k.em_tiles_x = (b.cur.width + t.w - 1) / t.w;
+  return k;
+}
+
+// Blocks of a persistent launch: every CU filled to the kernel's occupancy
+// (queried once per device, kernel and LDS size).
+pg_status persistent_blocks(const void *kernel, int threads, size_t lds, int &blocks) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void *, size_t>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(PG_ERR_HIP, "pg_frame_batched: no current device");
+  const auto key = std::make_tuple(dev, kernel, lds);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(key);
+  if (it == cache.end()) {
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, lds) != hipSuccess)
+      return fail(PG_ERR_HIP, "pg_frame_batched: device query failed: %s", hipGetErrorString(hipGetLastError()));
+    it = cache.emplace(key, cus * (per > 0 ? per : 1)).first;
+  }
+  blocks = it->second;
+  return PG_OK;
+}
+
+template <typename TG, int TW, int TH>
+pg_status launch_em_batched_t(const void *table, int dtype, int spp, hipStream_t st) {
+  const size_t lds = tile_lds(Tile{TW, TH}, spp);
+  int blocks = 0;
+  pg_status e = persistent_blocks((const void *)k_em_batched<TG, TW, TH>, TW * TH, lds, blocks);
+  if (e) return e;
+  hipLaunchKernelGGL((k_em_batched<TG, TW, TH>), dim3(blocks), dim3(TW * TH), lds, st, (const char *)table, dtype,
+                     spp);
+  return PG_OK;
+}
+
+template <typename TG>
+pg_status launch_em_batched(Tile t, const void *table, int dtype, int spp, hipStream_t st) {
+  if (t.w == 32 && t.h == 8) return launch_em_batched_t<TG, 32, 8>(table, dtype, spp, st);
+  if (t.w == 16 && t.h == 16) return launch_em_batched_t<TG, 16, 16>(table, dtype, spp, st);
+  if (t.w == 64 && t.h == 4) return launch_em_batched_t<TG, 64, 4>(table, dtype, spp, st);
+  if (t.w == 32 && t.h == 4) return launch_em_batched_t<TG, 32, 4>(table, dtype, spp, st);
+  if (t.w == 16 && t.h == 8) return launch_em_batched_t<TG, 16, 8>(table, dtype, spp, st);
+  if (t.w == 32 && t.h == 16) return launch_em_batched_t<TG, 32, 16>(table, dtype, spp, st);
+  if (t.w == 64 && t.h == 8) return launch_em_batched_t<TG, 64, 8>(table, dtype, spp, st);
+  return launch_em_batched_t<TG, 64, 2>(table, dtype, spp, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -324,16 +446,10 @@ pg_status pg_pdf(const pg_params *p, const pg_view *v, pg_gamma gamma, int32_t n
 pg_status pg_light_field(const pg_lights *lights, const pg_view *v, const uint8_t *vis, const pg_samples *samples,
                          void *stream) {
   pg_status st;
-  if (!lights) return fail(PG_ERR_ARG, "lights is NULL");
-  if (lights->count < 0 || lights->count > PG_MAX_LIGHTS) return fail(PG_ERR_ARG, "lights->count out of range");
-  if ((st = check_view(v, "view", false)) || (st = check_samples(samples, false, true))) return st;
-  if (!vis && lights->count > 0) return fail(PG_ERR_ARG, "vis is NULL");
-  LightsK L;
-  std::memset(&L, 0, sizeof(L));
-  L.count = lights->count;
-  L.ambient = lights->ambient;
-  for (int k = 0; k < lights->count; ++k)
-    for (int c = 0; c < 5; ++c) L.l[k][c] = lights->light[k][c];
+  if ((st = check_lights(lights, vis)) || (st = check_view(v, "view", false)) ||
+      (st = check_samples(samples, false, true)))
+    return st;
+  const LightsK L = to_k(lights);
   const ViewK V = to_k(v);
   const SamplesK S = to_k(samples);
   hipLaunchKernelGGL(k_light, stream_grid(V.W, V.H), dim3(64, 4), 0, (hipStream_t)stream, L, V, vis, S);
@@ -376,6 +492,73 @@ pg_status pg_nll_backward(const pg_params *p, const pg_view *v, const pg_samples
   const SamplesK S = to_k(in);
   launch_nll(t, P, V, S, theta, grad_out, grad_theta, nll, (hipStream_t)stream);
   return check_launch("pg_nll_backward");
+}
+
+size_t pg_batch_table_bytes(int32_t n_views) { return n_views < 1 ? 0 : batch_bytes(n_views); }
+
+pg_status pg_batch_pack(const pg_batch_view *views, int32_t n_views, void *host_table, size_t bytes) {
+  if (!views || n_views < 1) return fail(PG_ERR_ARG, "pg_batch_pack: no views");
+  if (n_views > (1 << 20)) return fail(PG_ERR_UNSUPPORTED, "pg_batch_pack: %d views", n_views);
+  if (!host_table || bytes < batch_bytes(n_views))
+    return fail(PG_ERR_ARG, "pg_batch_pack: table of %zu bytes, %zu needed", bytes, batch_bytes(n_views));
+  const int dtype = views[0].gamma_out.dtype;
+  int max_spp = 0;
+  pg_status st;
+  for (int i = 0; i < n_views; ++i) {
+    if ((st = in_view(check_batch_view(views[i], dtype), i))) return st;
+    if (!shared_params_equal(views[i].params, views[0].params))
+      return in_view(fail(PG_ERR_ARG, "parameters other than seed, frame and view differ from view 0's"), i);
+    for (int j = 0; j < i; ++j)
+      if (views[j].gamma_out.data == views[i].gamma_out.data || views[j].samples.dir == views[i].samples.dir)
+        return in_view(fail(PG_ERR_ARG, "output buffers shared with view %d", j), i);
+    if (views[i].samples.spp > max_spp) max_spp = views[i].samples.spp;
+  }
+  Tile t;
+  if ((st = pick_tile(&views[0].params, max_spp, t))) return st;
+  std::memset(host_table, 0, batch_bytes(n_views));
+  BatchViewK *out = reinterpret_cast<BatchViewK *>((char *)host_table + kBatchViewsOffset);
+  int64_t rs = 0, em = 0;
+  for (int i = 0; i < n_views; ++i) {
+    const pg_view &c = views[i].cur;
+    out[i] = to_batch(views[i], (int)rs, (int)em, t);
+    rs += (int64_t)((c.width + 63) / 64) * ((c.height + 3) / 4);
+    em += (int64_t)((c.width + t.w - 1) / t.w) * ((c.height + t.h - 1) / t.h);
+    if (rs >= ((int64_t)1 << 31) || em >= ((int64_t)1 << 31))
+      return fail(PG_ERR_UNSUPPORTED, "pg_batch_pack: too many tiles for 32-bit indexing");
+  }
+  BatchHeader *hd = reinterpret_cast<BatchHeader *>(host_table);
+  hd->n_views = n_views;
+  hd->rs_tiles = (int)rs;
+  hd->em_tiles = (int)em;
+  hd->dtype = dtype;
+  hd->max_spp = max_spp;
+  hd->tile_w = t.w;
+  hd->tile_h = t.h;
+  hd->pad = kBatchMagic;
+  hd->base = to_k(&views[0].params);
+  return ok();
+}
+
+pg_status pg_frame_batched(const void *host_table, void *device_table, size_t bytes, void *stream) {
+  if (!host_table || !device_table) return fail(PG_ERR_ARG, "pg_frame_batched: NULL table");
+  if (bytes < (size_t)kBatchViewsOffset) return fail(PG_ERR_ARG, "pg_frame_batched: table too small");
+  const BatchHeader hd = *reinterpret_cast<const BatchHeader *>(host_table);
+  if (hd.pad != kBatchMagic || hd.n_views < 1 || bytes < batch_bytes(hd.n_views))
+    return fail(PG_ERR_ARG, "pg_frame_batched: host_table was not packed by pg_batch_pack for %zu bytes", bytes);
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(device_table, host_table, batch_bytes(hd.n_views), hipMemcpyHostToDevice, s) != hipSuccess)
+    return fail(PG_ERR_HIP, "pg_frame_batched: table upload failed: %s", hipGetErrorString(hipGetLastError()));
+  const Tile t{hd.tile_w, hd.tile_h};
+  return dispatch_dtype(hd.dtype, [&](auto *tag) {
+    using TG = std::remove_pointer_t<decltype(tag)>;
+    int blocks = 0;
+    pg_status e = persistent_blocks((const void *)k_rs_batched<TG>, 256, 0, blocks);
+    if (e) return e;
+    hipLaunchKernelGGL((k_rs_batched<TG>), dim3(blocks), dim3(256), 0, s, (const char *)device_table, hd.dtype);
+    if ((e = check_launch("pg_frame_batched (sampling)"))) return e;
+    if ((e = launch_em_batched<TG>(t, device_table, hd.dtype, hd.max_spp, s))) return e;
+    return check_launch("pg_frame_batched (training)");
+  });
 }
 
 /* Diagnostic: Philox4x32-10 words for n counters (device arrays [n][4]). */

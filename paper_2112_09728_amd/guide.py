@@ -3,15 +3,21 @@
 ``Guide`` owns the per-view device state (two Gamma buffers used in turn, the
 sample records) and runs one frame of the path: reprojection and sampling
 (fused, or as two calls), the analytic light field that stands in for the
-trace, and the EM update.  ``NLLFunction`` puts the hand-written adjoint of
-the radiance-weighted mixture NLL behind ``torch.autograd``.
+trace, and the EM update.  ``BatchedGuide`` does the same for many views at
+once through pg_frame_batched, eagerly or by replaying captured graphs, and
+picks its training tile by timing the candidates.  ``NLLFunction`` puts the
+hand-written adjoint of the radiance-weighted mixture NLL behind
+``torch.autograd``.
 """
 from __future__ import annotations
 
 import torch
 
-from . import (PgParams, Samples, View, em_update, light_field, lights_struct, new_gamma, params,
-               reproject, reproject_sample, sample_mis, nll_backward)
+from . import (PgBatchView, PgParams, Samples, View, _gamma, batch_pack, batch_table_bytes, em_update,
+               frame_batched, light_field, lights_struct, new_gamma, params, reproject, reproject_sample,
+               sample_mis, nll_backward)
+
+TILES = ((32, 8), (16, 16), (64, 4), (32, 4), (16, 8), (64, 2), (32, 16), (64, 8))
 
 
 class DeviceFrame:
@@ -72,6 +78,115 @@ class Guide:
         self.cur = 1 - self.cur
         self.frame = t + 1
         return g_out
+
+
+class BatchedGuide:
+    """Many views stepped together: per frame one packed table and the two
+    persistent launches of pg_frame_batched, run eagerly or replayed from
+    captured graphs.
+
+    specs: one dict per view with width, height, spp, seed, lights, ambient
+    (and optionally view, the view id; default its position).  Two pinned host
+    tables are used in turn, so packing frame t+1 only waits for the upload of
+    frame t-1; each has its own captured graph.  The caller keeps the
+    DeviceFrames of the last two frames alive (the tables point at them)."""
+
+    def __init__(self, specs, gamma_dtype=torch.float16, device="cuda", tile=None, **param_overrides):
+        self.specs = [dict(s) for s in specs]
+        self.n = len(self.specs)
+        self.overrides = param_overrides
+        self.tile = tile
+        self.gamma = [[new_gamma(s["height"], s["width"], gamma_dtype, device),
+                       new_gamma(s["height"], s["width"], gamma_dtype, device)] for s in self.specs]
+        self.samples = [Samples(s["spp"], s["height"], s["width"], device) for s in self.specs]
+        self.lights = [lights_struct(s["lights"], s["ambient"]) for s in self.specs]
+        nbytes = batch_table_bytes(self.n)
+        self.host_tables = [torch.empty(nbytes, dtype=torch.uint8, pin_memory=True) for _ in range(2)]
+        self.dev_table = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.graphs = [None, None]
+        self.done = [None, None]
+        self.keep = [None, None]
+        self.slot = 0
+        self.cur = 0
+        self.frame = 0
+
+    def state(self, i: int):
+        return self.gamma[i][self.cur]
+
+    def _views(self, frames, t: int):
+        out = []
+        tw, th = self.tile if self.tile else (0, 0)
+        for i, (s, (cur, prev)) in enumerate(zip(self.specs, frames)):
+            b = PgBatchView()
+            b.params = params(s["seed"], frame=t, view=s.get("view", i), tile_w=tw, tile_h=th,
+                              **self.overrides)
+            b.cur = cur.view.c
+            if t > 0:
+                b.prev = prev.view.c
+                b.gamma_in = _gamma(self.gamma[i][self.cur])
+            b.gamma_out = _gamma(self.gamma[i][1 - self.cur])
+            b.samples = self.samples[i].c
+            b.vis = cur.vis.data_ptr()
+            b.lights = self.lights[i]
+            out.append(b)
+        return out
+
+    def _pack(self, frames, t: int, slot: int):
+        if self.done[slot] is not None:
+            self.done[slot].synchronize()  # the upload that read this table has run
+        batch_pack(self._views(frames, t), self.host_tables[slot])
+        self.keep[slot] = frames
+
+    def _run(self, slot: int, graph: bool):
+        if graph:
+            if self.graphs[slot] is None:
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, capture_error_mode="thread_local"):
+                    frame_batched(self.host_tables[slot], self.dev_table)
+                self.graphs[slot] = g
+            self.graphs[slot].replay()
+        else:
+            frame_batched(self.host_tables[slot], self.dev_table)
+        ev = torch.cuda.Event()
+        ev.record()
+        self.done[slot] = ev
+
+    def step(self, frames, t: int | None = None, graph: bool = False):
+        """One frame of every view.  frames: per view (cur, prev) DeviceFrames
+        (prev may be None at frame 0)."""
+        t = self.frame if t is None else t
+        slot = self.slot
+        self._pack(frames, t, slot)
+        self._run(slot, graph)
+        self.slot = 1 - slot
+        self.cur = 1 - self.cur
+        self.frame = t + 1
+
+    def autotune(self, frames, t: int | None = None, reps: int = 3, candidates=TILES):
+        """Time the batched frame for each training tile that fits (the frame
+        is recomputed from the same inputs each time, so the state is not
+        advanced) and keep the fastest.  Returns {tile: ms}."""
+        t = self.frame if t is None else t
+        times = {}
+        saved = self.tile
+        for tile in candidates:
+            self.tile = tile
+            try:
+                self._pack(frames, t, self.slot)
+            except RuntimeError:
+                continue  # does not fit this batch's spp
+            self._run(self.slot, graph=False)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                frame_batched(self.host_tables[self.slot], self.dev_table)
+            b.record()
+            torch.cuda.synchronize()
+            times[tile] = a.elapsed_time(b) / reps
+        self.tile = min(times, key=times.get) if times else saved
+        self.graphs = [None, None]  # captured with the previous tile
+        return times
 
 
 class NLLFunction(torch.autograd.Function):

@@ -195,6 +195,18 @@ class Sequence:
         return out
 
 
+def batched_views(n_views: int, sizes, spp_range, seed: int):
+    """Views of a batched workload: size uniform over `sizes`, spp uniform
+    over spp_range (inclusive), one seed per view.  Returns [(W, H, spp, seed)]."""
+    rng = np.random.default_rng([seed, 0xBA7C4])
+    out = []
+    for i in range(n_views):
+        w, h = sizes[int(rng.integers(len(sizes)))]
+        spp = int(rng.integers(spp_range[0], spp_range[1] + 1))
+        out.append((int(w), int(h), spp, seed + 1000 * (i + 1)))
+    return out
+
+
 def crop_scene(scene: dict, x0: int, y0: int, x1: int, y1: int) -> dict:
     """A sub-rectangle of a scene as a scene of its own (same lights)."""
     out = dict(scene)

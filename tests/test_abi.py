@@ -21,7 +21,7 @@ no_device = pytest.mark.skipif(torch.cuda.is_available(),
 
 def declared_functions():
     src = open(HEADER).read()
-    return sorted(set(re.findall(r"^(?:pg_status|const char \*)\s*(pg_\w+)\(", src, re.M)))
+    return sorted(set(re.findall(r"^(?:pg_status|const char \*|size_t)\s*(pg_\w+)\(", src, re.M)))
 
 
 def test_header_declarations_are_exported():
@@ -131,3 +131,78 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(pg, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(pg.LibraryMissing):
         pg.lib()
+
+
+def _bview(w=8, h=4, spp=1, frame=1, dtype=pg.PG_F32, base=0, **params):
+    """A batch view on fake pointers (pg_batch_pack only validates and packs)."""
+    b = pg.PgBatchView()
+    b.params = pg.params(3, frame=frame, **params)
+    b.cur = _view(w, h)
+    b.prev = _view(w, h)
+    b.gamma_in = pg.PgGamma(dtype, FAKE + base + 1024)
+    b.gamma_out = pg.PgGamma(dtype, FAKE + base + 2048)
+    b.samples = pg.PgSamples(spp, FAKE + base + 4096, FAKE, FAKE, FAKE, FAKE)
+    b.vis = FAKE
+    b.lights.count = 1
+    return b
+
+
+def _pack(views, nbytes=None):
+    n = len(views)
+    nbytes = pg.batch_table_bytes(n) if nbytes is None else nbytes
+    table = torch.zeros(max(nbytes, 1), dtype=torch.uint8)
+    arr = (pg.PgBatchView * n)(*views) if n else None
+    st = pg.lib().pg_batch_pack(arr, n, C.c_void_p(table.data_ptr()), nbytes)
+    return st, pg.lib().pg_last_error().decode(), table
+
+
+def test_batch_pack_layout_and_tile_counts():
+    """Host-only packing: the header counts the 64x4 sampling tiles and the
+    training tiles of every view, and takes the largest spp."""
+    sizes = [(70, 37, 1), (129, 64, 3), (33, 95, 8), (640, 360, 2)]
+    views = [_bview(w, h, spp, base=i << 16, tile_w=32, tile_h=4) for i, (w, h, spp) in enumerate(sizes)]
+    st, msg, table = _pack(views)
+    assert st == pg.PG_OK, msg
+    hd = table[:32].view(torch.int32).tolist()
+    n, rs, em, dtype, max_spp, tw, th, magic = hd
+    assert (n, dtype, max_spp, tw, th) == (4, pg.PG_F32, 8, 32, 4)
+    assert rs == sum(-(-w // 64) * -(-h // 4) for w, h, _ in sizes)
+    assert em == sum(-(-w // 32) * -(-h // 4) for w, h, _ in sizes)
+    assert magic == 0x31424750
+    assert pg.batch_table_bytes(0) == 0
+    assert pg.batch_table_bytes(2) - pg.batch_table_bytes(1) == pg.batch_table_bytes(3) - pg.batch_table_bytes(2)
+
+
+def test_batch_pack_rejects_bad_batches():
+    ok = [_bview(base=0), _bview(base=1 << 16)]
+    assert _pack(ok)[0] == pg.PG_OK
+    bad_dtype = [_bview(base=0), _bview(base=1 << 16, dtype=pg.PG_F16)]
+    shared_out = [_bview(base=0), _bview(base=0)]
+    alias = [_bview()]
+    alias[0].gamma_in = alias[0].gamma_out
+    params_differ = [_bview(base=0), _bview(base=1 << 16, pi_hi=0.9)]
+    spp9 = [_bview(spp=9)]
+    no_albedo = [_bview()]
+    no_albedo[0].cur = _view(albedo=False)
+    cases = [
+        (bad_dtype, pg.PG_ERR_ARG, "view 1"),
+        (shared_out, pg.PG_ERR_ARG, "view 1"),
+        (alias, pg.PG_ERR_ARG, "view 0"),
+        (params_differ, pg.PG_ERR_ARG, "view 1"),
+        (spp9, pg.PG_ERR_ARG, "view 0"),
+        (no_albedo, pg.PG_ERR_ARG, "view 0"),
+        ([_bview(flags=pg.PG_EM_BATCH)], pg.PG_ERR_UNSUPPORTED, "view 0"),
+        # 32x8 training tiles with 8 spp need more than 64 KiB of LDS
+        ([_bview(spp=8, tile_w=32, tile_h=8)], pg.PG_ERR_UNSUPPORTED, "LDS"),
+    ]
+    for views, want, where in cases:
+        st, msg, _ = _pack(views)
+        assert st == want and where in msg, (st, msg)
+    # frame 0 needs no history
+    first = [_bview(frame=0)]
+    first[0].gamma_in = pg.PgGamma(pg.PG_F32, None)
+    first[0].prev = pg.PgView()
+    assert _pack(first)[0] == pg.PG_OK
+    # too small a table, and no views
+    assert _pack(ok, nbytes=pg.batch_table_bytes(2) - 1)[0] == pg.PG_ERR_ARG
+    assert _pack([])[0] == pg.PG_ERR_ARG

@@ -1,0 +1,182 @@
+"""The batched frame (pg_frame_batched): views of uneven size and spp stepped
+together through two persistent launches, eagerly and from captured graphs.
+
+Per view the batched results must be bit-identical to the plain calls
+(pg_reproject_sample, pg_light_field, pg_em_update) on the same inputs, which
+the other GPU tests hold to the oracle; one view is also checked against the
+oracle directly."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2112_09728_amd as pg
+from paper_2112_09728_amd import workload as wl
+from pgtest import (TOL_DIR, TOL_EM_FRAME, assert_gamma_close, compare_samples, host, records_host, rel_err,
+                    underflow_mask)
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+# (width, height, spp): ragged against every tile shape, spp 1..8
+VIEWS = [(70, 37, 1), (129, 64, 3), (33, 95, 8), (200, 17, 2), (64, 64, 5), (1, 1, 4), (97, 3, 7)]
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Views:
+    """Per view: a camera-pan sequence, its device frames, and the plain path."""
+
+    def __init__(self, sizes, seed0, dtype):
+        self.seqs, self.specs, self.plain, self.first = [], [], [], []
+        for i, (w, h, spp) in enumerate(sizes):
+            seed = seed0 + 17 * i
+            seq = wl.Sequence(w, h, seed)
+            fr0 = seq.frame(0)
+            self.first.append(fr0)
+            self.seqs.append(seq)
+            self.specs.append(dict(width=w, height=h, spp=spp, seed=seed, lights=fr0["lights"],
+                                   ambient=float(fr0["ambient"]), view=i))
+            self.plain.append(pg.Guide(w, h, fr0["lights"], float(fr0["ambient"]), spp=spp, seed=seed,
+                                       view_id=i, gamma_dtype=dtype))
+        self.host = [None] * len(sizes)
+        self.dev = [None] * len(sizes)
+
+    def advance(self, t):
+        """Device frames (cur, prev) of frame t for every view."""
+        out = []
+        for i, seq in enumerate(self.seqs):
+            fr = self.first[i] if t == 0 else seq.frame(t)
+            cur = pg.DeviceFrame(fr)
+            out.append((cur, self.dev[i] if t > 0 else None))
+            self.host[i] = fr
+            self.dev[i] = cur
+        return out
+
+    def step_plain(self, frames, t):
+        for g, (cur, prev) in zip(self.plain, frames):
+            g.step(cur, prev, frame=t)
+
+
+def _assert_same(bg, views, t, what):
+    for i, g in enumerate(views.plain):
+        a, b = bg.state(i), g.state
+        assert torch.equal(a.view(torch.int16) if a.dtype != torch.float32 else a.view(torch.int32),
+                           b.view(torch.int16) if b.dtype != torch.float32 else b.view(torch.int32)), \
+            f"{what}: Gamma of view {i} differs at frame {t}"
+        sa, sb = bg.samples[i], g.samples
+        for name in ("dir", "pdf_mix", "pdf_brdf", "radiance"):
+            assert torch.equal(getattr(sa, name).view(torch.int32), getattr(sb, name).view(torch.int32)), \
+                f"{what}: {name} of view {i} differs at frame {t}"
+        assert torch.equal(sa.strategy, sb.strategy), f"{what}: strategy of view {i} differs at frame {t}"
+
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.float32, torch.bfloat16])
+def test_batched_equals_plain_calls(dtype):
+    say(f"case: batched vs plain, {len(VIEWS)} views, {dtype}")
+    views = Views(VIEWS, wl.SEED_BASE + 50, dtype)
+    bg = pg.BatchedGuide(views.specs, gamma_dtype=dtype, tile=(32, 4))
+    for t in range(4):
+        frames = views.advance(t)
+        bg.step(frames, t)
+        views.step_plain(frames, t)
+        torch.cuda.synchronize()
+        _assert_same(bg, views, t, "eager")
+    say("  4 frames bit-identical")
+
+
+def test_batched_graph_replays_match_eager():
+    """Two captured graphs (one per host table) replayed over 6 frames; between
+    replays the plain path runs eagerly on its own buffers and the host
+    synchronises; every replay must equal the plain path bit for bit."""
+    say("case: batched graph replays")
+    views = Views(VIEWS, wl.SEED_BASE + 60, torch.float16)
+    bg = pg.BatchedGuide(views.specs, gamma_dtype=torch.float16)
+    for t in range(6):
+        frames = views.advance(t)
+        bg.step(frames, t, graph=True)
+        views.step_plain(frames, t)
+        torch.cuda.synchronize()
+        _assert_same(bg, views, t, "graph replay")
+    assert bg.graphs[0] is not None and bg.graphs[1] is not None
+    say("  6 replays bit-identical")
+
+
+def test_batched_tiles_and_autotuner():
+    """Every training tile that fits gives the same bits; the autotuner times
+    them without advancing the state and keeps one that fits."""
+    say("case: batched tiles + autotuner")
+    sizes = [(70, 37, 1), (129, 64, 2), (33, 95, 3)]
+    views = Views(sizes, wl.SEED_BASE + 70, torch.float32)
+    frames0 = views.advance(0)
+    frames1 = views.advance(1)
+    ref = None
+    fitted = []
+    for tile in pg.guide.TILES:
+        bg = pg.BatchedGuide(views.specs, gamma_dtype=torch.float32, tile=tile)
+        try:
+            bg.step(frames0, 0)
+        except RuntimeError as e:
+            say(f"  tile {tile}: {e}")
+            continue
+        bg.step(frames1, 1)
+        torch.cuda.synchronize()
+        got = [host(bg.state(i)) for i in range(len(sizes))]
+        if ref is None:
+            ref = got
+        for a, b in zip(got, ref):
+            assert np.array_equal(a.view(np.int32), b.view(np.int32)), tile
+        fitted.append(tile)
+    assert len(fitted) >= 6, fitted
+    bg = pg.BatchedGuide(views.specs, gamma_dtype=torch.float32)
+    bg.step(frames0, 0)
+    torch.cuda.synchronize()
+    before = [host(bg.state(i)) for i in range(len(sizes))]
+    times = bg.autotune(frames1, 1, reps=2)
+    say("  autotuner (ms): " + ", ".join(f"{w}x{h} {ms:.3f}" for (w, h), ms in times.items()))
+    assert bg.tile in times and set(times) == set(fitted)
+    after = [host(bg.state(i)) for i in range(len(sizes))]
+    for a, b in zip(before, after):
+        assert np.array_equal(a.view(np.int32), b.view(np.int32))
+    bg.step(frames1, 1)
+    torch.cuda.synchronize()
+    for i in range(len(sizes)):
+        assert np.array_equal(host(bg.state(i)).view(np.int32), ref[i].view(np.int32))
+
+
+def test_batched_view_against_oracle():
+    """One view of a batch (5 spp, 97x61), frame 2, teacher-forced against the
+    FP64 oracle: directions, then the EM update from the GPU's records."""
+    say("case: batched view vs oracle")
+    sizes = [(40, 30, 1), (97, 61, 5), (64, 9, 2)]
+    views = Views(sizes, wl.SEED_BASE + 80, torch.float32)
+    bg = pg.BatchedGuide(views.specs, gamma_dtype=torch.float32)
+    i = 1
+    for t in range(3):
+        prev_fr = views.host[i]
+        frames = views.advance(t)
+        g_prev = bg.state(i).clone()
+        bg.step(frames, t)
+        torch.cuda.synchronize()
+    fr, spec = views.host[i], views.specs[i]
+    P = O.params(spec["seed"], frame=2, view=i)
+    v = O.OView(fr, fr["motion"], fr["disocc"])
+    vp = O.OView(prev_fr, prev_fr["motion"], prev_fr["disocc"])
+    g1, _ = O.reproject(P, v, vp, host(g_prev))
+    rec = records_host(bg.samples[i])
+    ro = O.sample(P, v, g1, spec["spp"])
+    st, _ = compare_samples(rec, ro, scene=fr, gamma=g1)
+    say(f"  samples {st}")
+    assert st["dir_max"] <= TOL_DIR
+    ro_light = O.light(fr["lights"], float(fr["ambient"]), fr["vis"], rec["dir"], rec["strategy"])
+    live = (rec["strategy"] == 1) | (rec["strategy"] == 2)
+    assert (rec["radiance"][~live] == 0).all()
+    assert rel_err(rec["radiance"][live], ro_light[live]).max() <= 1e-5
+    g2, stats = O.em(P, v, rec, g1, with_stats=True)
+    e = assert_gamma_close(host(bg.state(i)), g2, TOL_EM_FRAME, mask=~underflow_mask(stats),
+                           what="batched view, frame 2")
+    say(f"  EM {e}")
