@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
 # Algorithmic bytes per pixel-frame (G = bytes of Gamma per pixel, S = spp):
 #   fused reproject + sample: reads mv 8, mask 1, z 4, n 12, roughness 4,
-#     omega_o 12 at p; z_prev 4, n_prev 12, Gamma_prev G at the source q;
+#     omega_o 12 at p (41); z_prev 4, n_prev 12, Gamma_prev G at the source q;
 #     writes Gamma' G and records 21 S (dir 12, D 4, p_b 4, strategy 1)
 #   EM: reads Gamma' G, n 12, omega_o 12, roughness 4, albedo 4 and records
 #     21 S (dir 12, L 4, p_b 4, strategy 1); writes Gamma G
@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
 
 def bytes_reproject_sample(G, S):
-    return 61 + 2 * G + 21 * S
+    return 57 + 2 * G + 21 * S
 
 
 def bytes_em(G, S):
