@@ -377,41 +377,52 @@ __device__ __forceinline__ int xcd_tile(int bid, int n) {
 
 template <int TW, int TH>
 __device__ __forceinline__ void stage_records(const ViewK &v, const SamplesK &S, float4 *lds, int tx0,
-                                              int ty0) {
-  constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH;
+                                              int ty0, int s0 = 0) {
+  constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH, NT = TW * TH;
+  constexpr int IT = (SA + NT - 1) / NT;  // records of one sample plane per thread
   const int plane = v.H * v.pitch;
   const int splane = S.spp * plane;
-  for (int e = threadIdx.x; e < SA; e += TW * TH) {
+  int gi[IT];
+  bool in[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int e = threadIdx.x + i * NT;
     // e < 2^13, so the float quotient floors exactly
     const int sy = (int)(((float)e + 0.5f) * (1.0f / SW));
     const int sx = e - sy * SW;
     const int gx = tx0 - kR + sx, gy = ty0 - kR + sy;
-    const bool in = gx >= 0 && gy >= 0 && gx < v.W && gy < v.H;
-    for (int s = 0; s < S.spp; ++s) {
-      float4 rec = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (in) {
-        const int o = (s * v.H + gy) * v.pitch + gx;
-        if (S.strat[o] == 1) {
-          // a BRDF sample's density is a normal number (at least s_d cos/pi
-          // of a valid draw, or the GGX density of the drawn normal)
-          const float p = S.pb[o];
-          if (p > 0.0f)
-            rec = make_float4(S.dir[o], S.dir[splane + o], S.dir[2 * splane + o],
-                              S.L[o] * frcp(fmaxf(p, 1.17549435e-38f)));
-        }
-      }
-      lds[s * SA + e] = rec;
-    }
+    in[i] = e < SA && gx >= 0 && gy >= 0 && gx < v.W && gy < v.H;
+    gi[i] = gy * v.pitch + gx;
   }
-}
-
-// LDS offset of each of the 49 positions of the pick window relative to the
-// pixel (position 24, the centre, is never used).
-template <int SW>
-__device__ __forceinline__ void fill_pick_offsets(short *off) {
-  if (threadIdx.x < kSide * kSide) {
-    const int o = threadIdx.x;
-    off[o] = (short)((o / kSide - kR) * SW + (o % kSide - kR));
+  for (int s = s0; s < S.spp; ++s) {
+    // every load of this sample plane is issued before the first use
+    uint8_t st[IT];
+    float px[IT], py[IT], pz[IT], pl[IT], pp[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      st[i] = 0;
+      px[i] = py[i] = pz[i] = pl[i] = pp[i] = 0.0f;
+      if (in[i]) {
+        const int o = s * plane + gi[i];
+        st[i] = S.strat[o];
+        pp[i] = S.pb[o];
+        px[i] = S.dir[o];
+        py[i] = S.dir[splane + o];
+        pz[i] = S.dir[2 * splane + o];
+        pl[i] = S.L[o];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int e = threadIdx.x + i * NT;
+      if (IT * NT == SA || e < SA) {
+        // a BRDF sample's density is a normal number (at least s_d cos/pi of
+        // a valid draw, or the GGX density of the drawn normal)
+        const bool ok = st[i] == 1 && pp[i] > 0.0f;
+        lds[s * SA + e] = ok ? make_float4(px[i], py[i], pz[i], pl[i] * frcp(fmaxf(pp[i], 1.17549435e-38f)))
+                             : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      }
+    }
   }
 }
 
@@ -463,10 +474,12 @@ __device__ __forceinline__ void em_visit(const EmCtx &c, float4 r, Accum &a) {
 // Pick m of a pixel: the 16-bit field m of the stream-1 Philox words gives a
 // code c uniform over (48 neighbours) x spp; returns the LDS index of that
 // candidate.  All products fit 24 bits (full-rate v_mul_u32_u24); the code is
-// split as c = o spp + s by (c ceil(2^16/spp)) >> 16, exact for c < 48 spp.
-template <int SA>
+// split as c = o spp + s by (c ceil(2^16/spp)) >> 16, exact for c < 48 spp,
+// and the neighbour o (centre skipped) of the 7x7 window sits at row o / 7 =
+// (37 o) >> 8 (exact for o < 49), column o mod 7.
+template <int SA, int SW>
 __device__ __forceinline__ int pick_entry(uint4 w4, int m, uint32_t cs, uint32_t inv_spp, uint32_t spp,
-                                          int own, const short *off) {
+                                          int own) {
   const int wsel = (m >> 1) & 3;
   const uint32_t word = wsel == 0 ? w4.x : wsel == 1 ? w4.y : wsel == 2 ? w4.z : w4.w;
   const uint32_t h = (m & 1) ? (word >> 16) : (word & 0xFFFFu);
@@ -474,187 +487,314 @@ __device__ __forceinline__ int pick_entry(uint4 w4, int m, uint32_t cs, uint32_t
   const uint32_t o0 = __umul24(c, inv_spp) >> 16;
   const uint32_t s = c - __umul24(o0, spp);
   const uint32_t o = o0 + (o0 >= (uint32_t)(kCand / 2) ? 1u : 0u);
-  return (int)__umul24(s, (uint32_t)SA) + own + off[o];
+  const uint32_t row = __umul24(o, 37u) >> 8;
+  return (int)__umul24(s, (uint32_t)SA) + own + (int)(o + __umul24(row, (uint32_t)(SW - kSide))) -
+         (kR * SW + kR);
+}
+
+// Number of neighbour picks N(k) = 5 + floor(15 (kMax - k) / kMax) (Sec. 4.2).
+__device__ __forceinline__ int n_picks(const ParamsK &P, int k) {
+  k = k < 0 ? 0 : (k > P.k_max ? P.k_max : k);
+  return 5 + (15 * (P.k_max - k)) / P.k_max;
 }
 
 // Training list of one pixel: the LDS indices of its kept candidates, in the
 // order of the training set (own samples by sample index, then picks by pick
-// index).  A candidate is kept when its staged record is a BRDF-strategy
-// sample inside the image.  Returns the list length.
+// index), stored in column `col` of the list area.  A candidate is kept when
+// its staged record is a BRDF-strategy sample inside the image.  Candidates
+// are examined eight at a time (one Philox call): their addresses are formed
+// in registers and their records read together, then appended without
+// branches (a rejected candidate's slot is overwritten by the next one; the
+// area has room for every candidate).  Returns the list length.
 template <int TW, int TH>
-__device__ __forceinline__ int build_list(const ParamsK &P, const float4 *lds, const short *off,
-                                          uint16_t *list, int lane, int lx, int ly, int k, int spp,
-                                          uint32_t pix) {
+__device__ __forceinline__ int build_list(const ParamsK &P, const float4 *lds, uint16_t *list, int col, int lx,
+                                          int ly, int npick, int spp, uint32_t pix) {
   constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH, NT = TW * TH;
-  k = k < 0 ? 0 : (k > P.k_max ? P.k_max : k);
-  const int npick = 5 + (15 * (P.k_max - k)) / P.k_max;
   const uint32_t cs = (uint32_t)(kCand * spp);
   const uint32_t inv_spp = (65536u + (uint32_t)spp - 1u) / (uint32_t)spp;
   const int own = (ly + kR) * SW + (lx + kR);
   int n = 0;
-  for (int s = 0; s < spp; ++s) {
-    const int e = s * SA + own;
-    if (lds[e].w != 0.0f) list[(n++) * NT + lane] = (uint16_t)e;
+  {
+    float wv[kMaxSpp];
+#pragma unroll
+    for (int s = 0; s < kMaxSpp; ++s) wv[s] = s < spp ? lds[s * SA + own].w : 0.0f;
+#pragma unroll
+    for (int s = 0; s < kMaxSpp; ++s)
+      if (s < spp) {
+        list[n * NT + col] = (uint16_t)(s * SA + own);
+        n += wv[s] != 0.0f ? 1 : 0;
+      }
   }
-  uint4 w4 = make_uint4(0, 0, 0, 0);
-  for (int m = 0; m < npick; ++m) {
-    if ((m & 7) == 0) w4 = philox4x32_10(pix, P.frame, (1u << 16) | (uint32_t)(m >> 3), P.view, P.key0, P.key1);
-    const int e = pick_entry<SA>(w4, m, cs, inv_spp, (uint32_t)spp, own, off);
-    if (lds[e].w != 0.0f) list[(n++) * NT + lane] = (uint16_t)e;
+  for (int m0 = 0; m0 < npick; m0 += 8) {
+    const uint4 w4 = philox4x32_10(pix, P.frame, (1u << 16) | (uint32_t)(m0 >> 3), P.view, P.key0, P.key1);
+    int e[8];
+    float wv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      e[j] = pick_entry<SA, SW>(w4, j, cs, inv_spp, (uint32_t)spp, own);
+      wv[j] = lds[e[j]].w;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (m0 + j < npick) {
+        list[n * NT + col] = (uint16_t)e[j];
+        n += wv[j] != 0.0f ? 1 : 0;
+      }
   }
   return n;
 }
 
-// Order the tile's pixels by decreasing work `len` (0 .. kMaxLen - 1) so that
-// the lanes of a wave carry nearly equal work (the order inside a class is
-// irrelevant: a pixel's arithmetic does not depend on the lane it runs on).
-// The k-th heaviest group of 64 pixels goes to wave (k + block) mod waves,
-// so that the heavy waves of the blocks resident on a CU do not all land on
-// the same SIMD.  Returns the tile-local pixel index this lane works on.
+// Counting sort of the tile's items by decreasing work `len` (0 .. kMaxLen -
+// 1) so that the lanes of a wave carry nearly equal work (the order inside a
+// class is irrelevant: a pixel's arithmetic does not depend on the lane that
+// runs it).  The k-th heaviest group of 64 items goes to wave (k + rot) mod
+// waves, so that the heavy waves of the blocks resident on a CU do not all
+// land on the same SIMD.  cnt[0 .. kMaxLen) must be zero and visible to the
+// block on entry.  Each thread offers `item`; returns the item this lane
+// takes.
 constexpr int kMaxLen = kMaxSpp + 21;
 
 template <int NT>
-__device__ __forceinline__ int balance(int len, int *cnt, int *perm, int rot) {
-  const int t = threadIdx.x;
-  if (t < kMaxLen) cnt[t] = 0;
-  __syncthreads();
+__device__ __forceinline__ int balance(int len, int item, int *cnt, int *perm, int rot) {
+  static_assert(kMaxLen <= 32, "one half-wave scans the classes");
   const int rank = atomicAdd(&cnt[len], 1);
   __syncthreads();
-  if (t == 0) {
-    int acc = 0;
-    for (int b = kMaxLen - 1; b >= 0; --b) {
-      const int c = cnt[b];
-      cnt[b] = acc;
-      acc += c;
+  if (threadIdx.x < 64) {
+    // wave 0: cnt[b] <- items in the classes heavier than b (suffix scan)
+    const int l = threadIdx.x;
+    const int c = l < kMaxLen ? cnt[l] : 0;
+    int x = c;
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+      const int y = __shfl_down(x, d, 64);
+      if (l + d < 32) x += y;
     }
+    if (l < kMaxLen) cnt[l] = x - c;
   }
   __syncthreads();
   constexpr int NW = NT / 64;
   const int pos = cnt[len] + rank;                                // rank in the sorted order
   const int wave = NW > 1 ? ((pos >> 6) + rot) % NW : 0;
-  perm[wave * 64 + (pos & 63)] = t;
+  perm[wave * 64 + (pos & 63)] = item;
   __syncthreads();
-  return perm[t];
+  return perm[threadIdx.x];
 }
 
-// LDS of one training tile besides the dynamic records/lists area.
+// LDS of one training tile besides the dynamic records/state/lists area.
 template <int NT>
 struct EmShared {
-  int cnt[kMaxLen];
+  int cnt[2][kMaxLen];
   int perm[NT];
-  short off[kSide * kSide];
+  uint8_t work[NT];  // per pixel: candidate count, then list length
 };
 
-// One training tile: stage the records of the tile and its halo, sort the
-// pixels by candidate count, build each pixel's training list and run the
-// E- and M-steps.  Every thread of the block calls it (it synchronises); no
-// thread returns early, so a persistent block can loop over tiles.
+// One thread's share of a training tile's inputs, held in registers while
+// the loads are in flight: the state of its pixel (natural order) and its
+// records of sample plane 0.
+template <int TW, int TH>
+struct EmInput {
+  static constexpr int SW = TW + 2 * kR, SA = SW * (TH + 2 * kR), NT = TW * TH, IT = (SA + NT - 1) / NT;
+  float g[8], alb, rough;
+  V3 n, o;
+  uint32_t st[IT];
+  float px[IT], py[IT], pz[IT], pl[IT], pp[IT];
+};
+
+// Issue the loads of a tile's inputs (no use of the results here).
 template <typename TG, int TW, int TH>
-__device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const SamplesK &S, TG *gamma,
-                                        int iterations, int batch, int tx0, int ty0, int rot,
-                                        float4 *lds, EmShared<TW * TH> &sh) {
-  constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH, NT = TW * TH;
-  uint16_t *list = reinterpret_cast<uint16_t *>(lds + S.spp * SA);
-  stage_records<TW, TH>(v, S, lds, tx0, ty0);
-  fill_pick_offsets<SW>(sh.off);
+__device__ __forceinline__ void em_load(const ViewK &v, const SamplesK &S, const TG *gamma, int tx0, int ty0,
+                                        EmInput<TW, TH> &R) {
+  using In = EmInput<TW, TH>;
   const int plane = v.H * v.pitch;
-  // natural pixel order: the number of candidates of this lane's pixel
-  // (0 when it is not trained)
-  int ncand = 0;
-  {
-    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
-    const int x = tx0 + lx, y = ty0 + ly;
-    if (x < v.W && y < v.H) {
-      const int idx = y * v.pitch + x;
-      const bool guided = dot3(load3(v.n, plane, idx), load3(v.o, plane, idx)) > 0.0f &&
-                          v.rough[idx] >= P.rough_min;
-      if (guided) {
-        int kk = (int)GammaIO<TG>::load(gamma + 7 * plane + idx);
-        kk = kk < 0 ? 0 : (kk > P.k_max ? P.k_max : kk);
-        ncand = S.spp + 5 + (15 * (P.k_max - kk)) / P.k_max;
-      }
+  const int t = threadIdx.x;
+  const int x0 = tx0 + t % TW, y0 = ty0 + t / TW;
+  R.alb = R.rough = 0.0f;
+  R.n = R.o = V3{0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < 8; ++c) R.g[c] = 0.0f;
+  if (x0 < v.W && y0 < v.H) {
+    const int idx0 = y0 * v.pitch + x0;
+    gamma_load(gamma, plane, idx0, R.g);
+    R.alb = v.alb[idx0];
+    R.rough = v.rough[idx0];
+    R.n = load3(v.n, plane, idx0);
+    R.o = load3(v.o, plane, idx0);
+  }
+  const int splane = S.spp * plane;
+#pragma unroll
+  for (int i = 0; i < In::IT; ++i) {
+    const int e = t + i * In::NT;
+    // e < 2^13, so the float quotient floors exactly
+    const int sy = (int)(((float)e + 0.5f) * (1.0f / In::SW));
+    const int sx = e - sy * In::SW;
+    const int gx = tx0 - kR + sx, gy = ty0 - kR + sy;
+    R.st[i] = 0;
+    R.px[i] = R.py[i] = R.pz[i] = R.pl[i] = R.pp[i] = 0.0f;
+    if (e < In::SA && gx >= 0 && gy >= 0 && gx < v.W && gy < v.H) {
+      const int o = gy * v.pitch + gx;
+      R.st[i] = S.strat[o];
+      R.pp[i] = S.pb[o];
+      R.px[i] = S.dir[o];
+      R.py[i] = S.dir[splane + o];
+      R.pz[i] = S.dir[2 * splane + o];
+      R.pl[i] = S.L[o];
     }
   }
-  // pixels by decreasing candidate count; the barriers inside also publish
-  // the staged records
-  const int me = balance<NT>(ncand, sh.cnt, sh.perm, rot);
-  const int lx = me % TW, ly = me / TW;
-  const int x = tx0 + lx, y = ty0 + ly;
-  const int idx = y * v.pitch + x;
-  bool active = x < v.W && y < v.H;
-  float g[8];
-  V3 n = V3{0, 0, 0}, o = V3{0, 0, 0};
-  float rough = 0.0f;
-  if (active) {
-    gamma_load(gamma, plane, idx, g);
-    n = load3(v.n, plane, idx);
-    o = load3(v.o, plane, idx);
-    rough = v.rough[idx];
-    active = dot3(n, o) > 0.0f && rough >= P.rough_min;
-  }
-  // training list of this pixel, kept in this lane's column of the list area
-  int len = 0;
-  if (active)
-    len = build_list<TW, TH>(P, lds, sh.off, list, threadIdx.x, lx, ly, (int)g[7], S.spp,
-                             (uint32_t)(y * v.W + x));
-  if (len == 0) return;  // no training sample (or no pixel): the model stays as it is
-  EmCtx c;
-  c.px = make_pixel(P, n, o, rough, v.alb[idx]);
-  const int iters = batch ? iterations : 1;
-  for (int it = 0; it < iters; ++it) {
-    c.G = gauss_setup(g[0], g[1], g[2], g[3], g[4], P.eps);
-    c.pi = g[5];
-    c.one_m_pi = 1.0f - g[5];
-    Accum a = {0, 0, 0, 0, 0, 0, 0};
-    for (int j = 0; j < len; ++j) em_visit(c, lds[list[j * NT + threadIdx.x]], a);
-    if (!(a.B0 > 0.0f)) break;
-    if (!batch) {
-      // stepwise merge with eta = 1/(k+1) and evidence W; only ratios of
-      // evidences appear, so a subnormal B1 is harmless
-      const float eta = frcp(g[7] + 1.0f);  // k + 1 in [1, kMax + 1]
-      const float sw = fmaf(1.0f - eta, g[6], eta * a.B0);
-      const float so = (1.0f - eta) * g[5] * g[6];
-      const float sn = eta * a.B1;
-      const float sg = so + sn;
-      if (sg > 0.0f && a.B1 > 0.0f) {
-        const float al = so / sg, be = sn / sg;
-        const float dx = g[0] - a.mx, dy = g[1] - a.my;
-        const float ab = al * be;
-        g[0] = fmaf(al, g[0], be * a.mx);
-        g[1] = fmaf(al, g[1], be * a.my);
-        g[2] = fmaf(ab * dx, dx, fmaf(al, g[2], be * a.sxx));
-        g[3] = fmaf(ab * dx, dy, fmaf(al, g[3], be * a.sxy));
-        g[4] = fmaf(ab * dy, dy, fmaf(al, g[4], be * a.syy));
-      }
-      float pn = sg / sw;
-      if (!(P.flags & kNoClamp)) pn = fminf(fmaxf(pn, P.pi_lo), P.pi_hi);
-      g[5] = pn;
-      g[6] = sw;
-      g[7] = fminf(g[7] + 1.0f, (float)P.k_max);
-    } else {
-      if (a.B1 > 0.0f) {
-        g[0] = a.mx;
-        g[1] = a.my;
-        g[2] = a.sxx;
-        g[3] = a.sxy;
-        g[4] = a.syy;
-      }
-      float pn = a.B1 / a.B0;
-      if (!(P.flags & kNoClamp)) pn = fminf(fmaxf(pn, P.pi_lo), P.pi_hi);
-      g[5] = pn;
-    }
-  }
-  gamma_store(gamma, plane, idx, g);
 }
 
+// One training tile.  Its inputs arrive in R (state of each pixel in natural
+// order, records of plane 0; further planes are staged here): stage the
+// records in LDS; sort the pixels by candidate count and build each pixel's
+// training list; sort them again by list length and run the E- and M-steps
+// (the lane of a pixel re-reads its state, which the natural-order load has
+// just brought into the caches); write the tile's Gamma back in natural order
+// through LDS (full cache lines).  Every thread of the block calls it and
+// none leaves early; a block that runs several tiles synchronises between
+// them (the write-back area overlaps the records).
+// Dynamic LDS: records [spp][SH][SW] float4, then lists [spp + 20][NT]
+// uint16; the write-back reuses the area ([8][NT] float).
+template <typename TG, int TW, int TH>
+__device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const SamplesK &S, TG *gamma,
+                                        int iterations, int batch, int tx0, int ty0, int rot, float4 *lds,
+                                        EmShared<TW * TH> &sh, const EmInput<TW, TH> &R) {
+  constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH, NT = TW * TH, IT = EmInput<TW, TH>::IT;
+  uint16_t *list = reinterpret_cast<uint16_t *>(lds + S.spp * SA);
+  float *wb = reinterpret_cast<float *>(lds);  // write-back area, once the records are no longer read
+  const int plane = v.H * v.pitch;
+  const int t = threadIdx.x;
+  const int x0 = tx0 + t % TW, y0 = ty0 + t / TW;
+  const bool in_image = x0 < v.W && y0 < v.H;
+  if (t < 2 * kMaxLen) (&sh.cnt[0][0])[t] = 0;
+  // plane-0 records to LDS
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int e = t + i * NT;
+    if (IT * NT == SA || e < SA) {
+      // a BRDF sample's density is a normal number (at least s_d cos/pi of a
+      // valid draw, or the GGX density of the drawn normal)
+      const bool ok = R.st[i] == 1 && R.pp[i] > 0.0f;
+      lds[e] = ok ? make_float4(R.px[i], R.py[i], R.pz[i], R.pl[i] * frcp(fmaxf(R.pp[i], 1.17549435e-38f)))
+                  : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+  }
+  if (S.spp > 1) stage_records<TW, TH>(v, S, lds, tx0, ty0, 1);
+  // the number of candidates of this lane's pixel (0 when it is not trained)
+  int ncand = 0;
+  if (in_image && dot3(R.n, R.o) > 0.0f && R.rough >= P.rough_min) ncand = S.spp + n_picks(P, (int)R.g[7]);
+  sh.work[t] = (uint8_t)ncand;
+  __syncthreads();
+  // lists: pixels by decreasing candidate count
+  int me;
+  {
+    const int pa = balance<NT>(ncand, t, sh.cnt[0], sh.perm, rot);
+    const int nc = sh.work[pa];
+    int len = 0;
+    if (nc > 0) {
+      const int lx = pa % TW, ly = pa / TW;
+      len = build_list<TW, TH>(P, lds, list, pa, lx, ly, nc - S.spp, S.spp,
+                               (uint32_t)((ty0 + ly) * v.W + tx0 + lx));
+    }
+    sh.work[pa] = (uint8_t)len;
+    // E- and M-steps: pixels by decreasing list length
+    me = balance<NT>(len, pa, sh.cnt[1], sh.perm, rot + 1);
+  }
+  const int len = sh.work[me];
+  EmCtx c;
+  float g[8];
+  if (len > 0) {
+    const int idx = (ty0 + me / TW) * v.pitch + tx0 + me % TW;
+    gamma_load(gamma, plane, idx, g);
+    c.px = make_pixel(P, load3(v.n, plane, idx), load3(v.o, plane, idx), v.rough[idx], v.alb[idx]);
+  }
+  if (len > 0) {  // otherwise no training sample (or no pixel): the model stays as it is
+    const int iters = batch ? iterations : 1;
+    for (int it = 0; it < iters; ++it) {
+      c.G = gauss_setup(g[0], g[1], g[2], g[3], g[4], P.eps);
+      c.pi = g[5];
+      c.one_m_pi = 1.0f - g[5];
+      Accum a = {0, 0, 0, 0, 0, 0, 0};
+      for (int j = 0; j < len; ++j) em_visit(c, lds[list[j * NT + me]], a);
+      if (!(a.B0 > 0.0f)) break;
+      if (!batch) {
+        // stepwise merge with eta = 1/(k+1) and evidence W; only ratios of
+        // evidences appear, so a subnormal B1 is harmless
+        const float eta = frcp(g[7] + 1.0f);  // k + 1 in [1, kMax + 1]
+        const float sw = fmaf(1.0f - eta, g[6], eta * a.B0);
+        const float so = (1.0f - eta) * g[5] * g[6];
+        const float sn = eta * a.B1;
+        const float sg = so + sn;
+        if (sg > 0.0f && a.B1 > 0.0f) {
+          const float al = so / sg, be = sn / sg;
+          const float dx = g[0] - a.mx, dy = g[1] - a.my;
+          const float ab = al * be;
+          g[0] = fmaf(al, g[0], be * a.mx);
+          g[1] = fmaf(al, g[1], be * a.my);
+          g[2] = fmaf(ab * dx, dx, fmaf(al, g[2], be * a.sxx));
+          g[3] = fmaf(ab * dx, dy, fmaf(al, g[3], be * a.sxy));
+          g[4] = fmaf(ab * dy, dy, fmaf(al, g[4], be * a.syy));
+        }
+        float pn = sg / sw;
+        if (!(P.flags & kNoClamp)) pn = fminf(fmaxf(pn, P.pi_lo), P.pi_hi);
+        g[5] = pn;
+        g[6] = sw;
+        g[7] = fminf(g[7] + 1.0f, (float)P.k_max);
+      } else {
+        if (a.B1 > 0.0f) {
+          g[0] = a.mx;
+          g[1] = a.my;
+          g[2] = a.sxx;
+          g[3] = a.sxy;
+          g[4] = a.syy;
+        }
+        float pn = a.B1 / a.B0;
+        if (!(P.flags & kNoClamp)) pn = fminf(fmaxf(pn, P.pi_lo), P.pi_hi);
+        g[5] = pn;
+      }
+    }
+  }
+  __syncthreads();  // records and lists are no longer read
+  if (len > 0) {
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) wb[ch * NT + me] = g[ch];
+  }
+  __syncthreads();
+  if (in_image) {
+    float go[8];
+    const bool changed = sh.work[t] > 0;
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) go[ch] = changed ? wb[ch * NT + t] : R.g[ch];
+    gamma_store(gamma, plane, y0 * v.pitch + x0, go);
+  }
+}
+
+// Static persistent schedule: the blocks of XCD j (ids j, j + 8, ...) walk
+// the j-th of 8 contiguous bands of the tile list, so that neighbouring tiles
+// share that XCD's L2.
+struct TileBand {
+  int first, end, step;
+  __device__ TileBand(int n_tiles) {
+    const int G = (int)gridDim.x, nb = G < 8 ? G : 8;
+    const int band = (int)blockIdx.x % nb, slot = (int)blockIdx.x / nb;
+    step = (G - band + nb - 1) / nb;
+    first = (int)((long long)n_tiles * band / nb) + slot;
+    end = (int)((long long)n_tiles * (band + 1) / nb);
+  }
+};
+
+// One tile per block (blocks are mapped to XCD bands by xcd_tile); with the
+// LDS and registers of a tile, several blocks share each CU, which hides the
+// loads of one block behind the arithmetic of the others better than a
+// persistent loop with register prefetch.
 template <typename TG, int TW, int TH>
 __global__ __launch_bounds__(TW *TH) void k_em(ParamsK P, ViewK v, SamplesK S, TG *__restrict__ gamma,
                                                int iterations, int batch, int tiles_x, int n_tiles) {
-  extern __shared__ float4 lds[];  // records [spp][SH][SW], then lists [spp + 20][NT]
+  extern __shared__ float4 lds[];  // records, state and lists (see em_tile)
   __shared__ EmShared<TW * TH> sh;
   const int tile = xcd_tile(blockIdx.x, n_tiles);
-  em_tile<TG, TW, TH>(P, v, S, gamma, iterations, batch, (tile % tiles_x) * TW, (tile / tiles_x) * TH,
-                      (int)blockIdx.x, lds, sh);
+  const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
+  EmInput<TW, TH> R;
+  em_load(v, S, gamma, tx0, ty0, R);
+  em_tile<TG, TW, TH>(P, v, S, gamma, iterations, batch, tx0, ty0, (int)blockIdx.x, lds, sh, R);
 }
 
 // ---------------------------------------------------------------------------
@@ -698,12 +838,10 @@ __global__ __launch_bounds__(TW *TH) void k_nll(ParamsK P, ViewK v, SamplesK S, 
                                                 const float *__restrict__ grad_out, float *__restrict__ grad,
                                                 float *__restrict__ nll, int tiles_x, int n_tiles) {
   extern __shared__ float4 lds[];
-  __shared__ short s_off[kSide * kSide];
   constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH;
   const int tile = xcd_tile(blockIdx.x, n_tiles);
   const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
   stage_records<TW, TH>(v, S, lds, tx0, ty0);
-  fill_pick_offsets<SW>(s_off);
   __syncthreads();
   const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
   const int x = tx0 + lx, y = ty0 + ly;
@@ -735,7 +873,7 @@ __global__ __launch_bounds__(TW *TH) void k_nll(ParamsK P, ViewK v, SamplesK S, 
     c.ic = A * idet;
     int k = (int)th[7];
     k = k < 0 ? 0 : (k > P.k_max ? P.k_max : k);
-    const int npick = 5 + (15 * (P.k_max - k)) / P.k_max;
+    const int npick = n_picks(P, k);
     const uint32_t pix = (uint32_t)(y * v.W + x);
     const uint32_t cs = (uint32_t)(kCand * S.spp);
     const uint32_t inv_spp = (65536u + (uint32_t)S.spp - 1u) / (uint32_t)S.spp;
@@ -744,7 +882,7 @@ __global__ __launch_bounds__(TW *TH) void k_nll(ParamsK P, ViewK v, SamplesK S, 
     uint4 w4 = make_uint4(0, 0, 0, 0);
     for (int m = 0; m < npick; ++m) {
       if ((m & 7) == 0) w4 = philox4x32_10(pix, P.frame, (1u << 16) | (uint32_t)(m >> 3), P.view, P.key0, P.key1);
-      nll_visit(c, lds[pick_entry<SA>(w4, m, cs, inv_spp, (uint32_t)S.spp, own, s_off)], a);
+      nll_visit(c, lds[pick_entry<SA, SW>(w4, m, cs, inv_spp, (uint32_t)S.spp, own)], a);
     }
     const float sc = grad_out ? grad_out[idx] : 1.0f;
     gr[0] = sc * a.gmx;
@@ -848,28 +986,27 @@ __global__ __launch_bounds__(256) void k_rs_batched(const char *__restrict__ tab
   }
 }
 
-// Persistent training over the TW x TH tiles of all views.  The blocks on XCD
-// j (block ids j, j+8, ...) take the j-th eighth of the tile list in order,
-// so that neighbouring tiles share that XCD's L2.  `spp_cap` is the spp the
-// dynamic LDS was sized for: a table that needs more is not processed.
+// Persistent training over the TW x TH tiles of all views: the blocks of XCD
+// j walk the j-th band of the tile list.  `spp_cap` is the spp the dynamic
+// LDS was sized for: a table that needs more is not processed.
 template <typename TG, int TW, int TH>
 __global__ __launch_bounds__(TW *TH) void k_em_batched(const char *__restrict__ table, int dtype, int spp_cap) {
   extern __shared__ float4 lds[];
   __shared__ EmShared<TW * TH> sh;
   const BatchHeader *hd = reinterpret_cast<const BatchHeader *>(table);
   if (hd->dtype != dtype || hd->max_spp > spp_cap || hd->tile_w != TW || hd->tile_h != TH) return;
-  const int n_views = hd->n_views, n_tiles = hd->em_tiles;
+  const int n_views = hd->n_views;
   const BatchViewK *vs = batch_views(table);
-  const int G = gridDim.x, xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-  const int per = (G - xcd + 7) >> 3;  // blocks on this XCD
-  const int lo = (int)((long long)n_tiles * xcd / 8), hi = (int)((long long)n_tiles * (xcd + 1) / 8);
-  for (int t = lo + slot; t < hi; t += per) {
-    __syncthreads();  // the previous tile's LDS is no longer read
+  const TileBand b(hd->em_tiles);
+  for (int t = b.first; t < b.end; t += b.step) {
+    __syncthreads();  // the previous tile's write-back has read the LDS
     const BatchViewK &bv = vs[batch_find<true>(vs, n_views, t)];
     const int l = t - bv.em_begin;
+    const int tx0 = (l % bv.em_tiles_x) * TW, ty0 = (l / bv.em_tiles_x) * TH;
     const ParamsK P = batch_params(hd->base, bv);
-    em_tile<TG, TW, TH>(P, bv.cur, bv.S, (TG *)bv.gout, 1, 0, (l % bv.em_tiles_x) * TW,
-                        (l / bv.em_tiles_x) * TH, t, lds, sh);
+    EmInput<TW, TH> R;
+    em_load(bv.cur, bv.S, (const TG *)bv.gout, tx0, ty0, R);
+    em_tile<TG, TW, TH>(P, bv.cur, bv.S, (TG *)bv.gout, 1, 0, tx0, ty0, t, lds, sh, R);
   }
 }
 

@@ -151,7 +151,8 @@ constexpr Tile kTiles[] = {{32, 8}, {16, 16}, {64, 4}, {32, 4}, {16, 8}, {64, 2}
 Tile default_tile(int spp) { return spp <= 4 ? Tile{32, 8} : Tile{32, 4}; }
 
 // Dynamic LDS of the training kernels: staged records [spp][h+6][w+6] float4
-// and the per-pixel training lists [spp+20][w*h] uint16.
+// and the training lists [spp+20][w*h] uint16 (at least 8 floats per pixel,
+// which the Gamma write-back reuses).
 size_t tile_lds(Tile t, int spp) {
   return (size_t)(t.w + 2 * kR) * (t.h + 2 * kR) * spp * sizeof(float4) +
          (size_t)(spp + 20) * t.w * t.h * sizeof(uint16_t);
@@ -173,26 +174,48 @@ pg_status pick_tile(const pg_params *p, int spp, Tile &t) {
   return PG_OK;
 }
 
+// Blocks of a persistent launch: every CU filled to the kernel's occupancy
+// (queried once per device, kernel and LDS size).
+pg_status persistent_blocks(const void *kernel, int threads, size_t lds, int &blocks) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void *, size_t>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(PG_ERR_HIP, "no current device");
+  const auto key = std::make_tuple(dev, kernel, lds);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(key);
+  if (it == cache.end()) {
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, lds) != hipSuccess)
+      return fail(PG_ERR_HIP, "device query failed: %s", hipGetErrorString(hipGetLastError()));
+    it = cache.emplace(key, cus * (per > 0 ? per : 1)).first;
+  }
+  blocks = it->second;
+  return PG_OK;
+}
+
 template <typename TG, int TW, int TH>
-void launch_em_t(const ParamsK &P, const ViewK &v, const SamplesK &S, TG *g, int iters, int batch,
-                 hipStream_t st) {
+pg_status launch_em_t(const ParamsK &P, const ViewK &v, const SamplesK &S, TG *g, int iters, int batch,
+                      hipStream_t st) {
   const int tx = (v.W + TW - 1) / TW, ty = (v.H + TH - 1) / TH;
   const int n = tx * ty;
   const size_t lds = tile_lds(Tile{TW, TH}, S.spp);
   hipLaunchKernelGGL((k_em<TG, TW, TH>), dim3(n), dim3(TW * TH), lds, st, P, v, S, g, iters, batch, tx, n);
+  return PG_OK;
 }
 
 template <typename TG>
-void launch_em(Tile t, const ParamsK &P, const ViewK &v, const SamplesK &S, TG *g, int iters, int batch,
-               hipStream_t st) {
-  if (t.w == 32 && t.h == 8) launch_em_t<TG, 32, 8>(P, v, S, g, iters, batch, st);
-  else if (t.w == 16 && t.h == 16) launch_em_t<TG, 16, 16>(P, v, S, g, iters, batch, st);
-  else if (t.w == 64 && t.h == 4) launch_em_t<TG, 64, 4>(P, v, S, g, iters, batch, st);
-  else if (t.w == 32 && t.h == 4) launch_em_t<TG, 32, 4>(P, v, S, g, iters, batch, st);
-  else if (t.w == 16 && t.h == 8) launch_em_t<TG, 16, 8>(P, v, S, g, iters, batch, st);
-  else if (t.w == 32 && t.h == 16) launch_em_t<TG, 32, 16>(P, v, S, g, iters, batch, st);
-  else if (t.w == 64 && t.h == 8) launch_em_t<TG, 64, 8>(P, v, S, g, iters, batch, st);
-  else launch_em_t<TG, 64, 2>(P, v, S, g, iters, batch, st);
+pg_status launch_em(Tile t, const ParamsK &P, const ViewK &v, const SamplesK &S, TG *g, int iters, int batch,
+                    hipStream_t st) {
+  if (t.w == 32 && t.h == 8) return launch_em_t<TG, 32, 8>(P, v, S, g, iters, batch, st);
+  if (t.w == 16 && t.h == 16) return launch_em_t<TG, 16, 16>(P, v, S, g, iters, batch, st);
+  if (t.w == 64 && t.h == 4) return launch_em_t<TG, 64, 4>(P, v, S, g, iters, batch, st);
+  if (t.w == 32 && t.h == 4) return launch_em_t<TG, 32, 4>(P, v, S, g, iters, batch, st);
+  if (t.w == 16 && t.h == 8) return launch_em_t<TG, 16, 8>(P, v, S, g, iters, batch, st);
+  if (t.w == 32 && t.h == 16) return launch_em_t<TG, 32, 16>(P, v, S, g, iters, batch, st);
+  if (t.w == 64 && t.h == 8) return launch_em_t<TG, 64, 8>(P, v, S, g, iters, batch, st);
+  return launch_em_t<TG, 64, 2>(P, v, S, g, iters, batch, st);
 }
 
 template <int TW, int TH>
@@ -289,27 +312,6 @@ BatchViewK to_batch(const pg_batch_view &b, int rs_begin, int em_begin, Tile t) 
   k.em_begin = em_begin;
   k.em_tiles_x = (b.cur.width + t.w - 1) / t.w;
   return k;
-}
-
-// Blocks of a persistent launch: every CU filled to the kernel's occupancy
-// (queried once per device, kernel and LDS size).
-pg_status persistent_blocks(const void *kernel, int threads, size_t lds, int &blocks) {
-  static std::mutex mu;
-  static std::map<std::tuple<int, const void *, size_t>, int> cache;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return fail(PG_ERR_HIP, "pg_frame_batched: no current device");
-  const auto key = std::make_tuple(dev, kernel, lds);
-  std::lock_guard<std::mutex> lock(mu);
-  auto it = cache.find(key);
-  if (it == cache.end()) {
-    int cus = 0, per = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, lds) != hipSuccess)
-      return fail(PG_ERR_HIP, "pg_frame_batched: device query failed: %s", hipGetErrorString(hipGetLastError()));
-    it = cache.emplace(key, cus * (per > 0 ? per : 1)).first;
-  }
-  blocks = it->second;
-  return PG_OK;
 }
 
 template <typename TG, int TW, int TH>
@@ -473,8 +475,8 @@ pg_status pg_em_update(const pg_params *p, const pg_view *v, const pg_samples *i
   hipStream_t s = (hipStream_t)stream;
   return dispatch_dtype(gamma_inout.dtype, [&](auto *tag) {
     using TG = std::remove_pointer_t<decltype(tag)>;
-    launch_em<TG>(t, P, V, S, (TG *)gamma_inout.data, iterations, batch, s);
-    return check_launch("pg_em_update");
+    pg_status e = launch_em<TG>(t, P, V, S, (TG *)gamma_inout.data, iterations, batch, s);
+    return e ? e : check_launch("pg_em_update");
   });
 }
 
