@@ -219,8 +219,10 @@ pg_status pg_nll_backward(const pg_params *p, const pg_view *v, const pg_samples
  * same training tile. */
 typedef struct pg_batch_view {
   pg_params params;    /* seed, frame and view may differ between views; every
-                          other field must equal view 0's (tile_w/tile_h of
-                          view 0 pick the training tile, 0 = default)        */
+                          other field must equal view 0's.  tile_w/tile_h of
+                          view 0 request a training tile: it is used for the
+                          views of every spp whose LDS it fits, the default
+                          tile of that spp elsewhere (0 = defaults)          */
   pg_view cur;         /* this frame's G-buffer (albedo required)             */
   pg_view prev;        /* previous frame's (read when params.frame > 0)       */
   pg_gamma gamma_in;   /* previous state (read when params.frame > 0)         */
@@ -237,19 +239,22 @@ size_t pg_batch_table_bytes(int32_t n_views);
 /* Checks n_views views (the same checks as the single-view calls, plus a
  * common dtype and shared parameters) and writes the packed table into
  * host_table (caller-owned host memory of at least pg_batch_table_bytes
- * bytes).  Host only: no GPU work, nothing retained. */
+ * bytes).  The table groups the views by spp; each group is trained by a
+ * launch of its own with its tile.  Host only: no GPU work, nothing
+ * retained. */
 pg_status pg_batch_pack(const pg_batch_view *views, int32_t n_views, void *host_table, size_t bytes);
 
 /* Enqueues on `stream`: a copy of `bytes` bytes from host_table to
- * device_table (caller-owned device memory), then the two persistent
- * launches, which read the table there.  The launch configuration (dtype,
- * training tile, largest spp) is read from host_table during the call.
- * host_table should be pinned (hipHostMalloc) so that the copy is
- * asynchronous and can be captured; it must not be re-packed before the copy
- * has run.  A captured graph replays re-packed tables of other frames and
- * views as long as dtype, tile and largest spp stay those of the capture (a
- * table that differs in them is skipped by the kernels: nothing is written).
- * Views must not share output buffers. */
+ * device_table (caller-owned device memory), then the persistent launches
+ * (sampling for all views, then training per spp group), which read the
+ * table there.  The launch configuration (dtype, spp groups and their tiles)
+ * is read from host_table during the call.  host_table should be pinned
+ * (hipHostMalloc) so that the copy is asynchronous and can be captured; it
+ * must not be re-packed before the copy has run.  A captured graph replays
+ * re-packed tables of other frames and views as long as the dtype and the spp
+ * groups with their tiles stay those of the capture (a group that differs is
+ * skipped by its kernel: nothing of it is written).  Views must not share
+ * output buffers. */
 pg_status pg_frame_batched(const void *host_table, void *device_table, size_t bytes, void *stream);
 
 /* Diagnostic: Philox4x32-10 (Salmon et al., SC 2011), the generator behind

@@ -916,9 +916,17 @@ struct BatchViewK {
   int rs_begin, rs_tiles_x, em_begin, em_tiles_x;
 };
 
+// The views of a table are ordered by spp; the views of one spp form a class
+// whose training tiles are contiguous in the tile list and run in a launch of
+// their own, with the tile shape and LDS of that spp.
+struct BatchClass {
+  int spp, tile_w, tile_h, em_begin, em_end, pad[3];
+};
+
 struct BatchHeader {
-  int n_views, rs_tiles, em_tiles, dtype, max_spp, tile_w, tile_h, pad;
+  int n_views, rs_tiles, em_tiles, dtype, n_classes, magic, pad[2];
   ParamsK base;  // fields shared by every view (key, frame, view come per view)
+  BatchClass cls[kMaxSpp];
 };
 
 constexpr int kBatchViewsOffset = (int)((sizeof(BatchHeader) + 63) / 64 * 64);
@@ -986,20 +994,25 @@ __global__ __launch_bounds__(256) void k_rs_batched(const char *__restrict__ tab
   }
 }
 
-// Persistent training over the TW x TH tiles of all views: the blocks of XCD
-// j walk the j-th band of the tile list.  `spp_cap` is the spp the dynamic
-// LDS was sized for: a table that needs more is not processed.
+// Persistent training over the TW x TH tiles of the views of class `cls`:
+// the blocks of XCD j walk the j-th band of the class's tiles.  `spp_cap` is
+// the spp the dynamic LDS was sized for; a table whose class differs from the
+// launch (tile, spp, dtype) is not processed.
 template <typename TG, int TW, int TH>
-__global__ __launch_bounds__(TW *TH) void k_em_batched(const char *__restrict__ table, int dtype, int spp_cap) {
+__global__ __launch_bounds__(TW *TH) void k_em_batched(const char *__restrict__ table, int dtype, int cls,
+                                                       int spp_cap) {
   extern __shared__ float4 lds[];
   __shared__ EmShared<TW * TH> sh;
   const BatchHeader *hd = reinterpret_cast<const BatchHeader *>(table);
-  if (hd->dtype != dtype || hd->max_spp > spp_cap || hd->tile_w != TW || hd->tile_h != TH) return;
+  if (hd->dtype != dtype || cls >= hd->n_classes) return;
+  const BatchClass c = hd->cls[cls];
+  if (c.spp > spp_cap || c.tile_w != TW || c.tile_h != TH) return;
   const int n_views = hd->n_views;
   const BatchViewK *vs = batch_views(table);
-  const TileBand b(hd->em_tiles);
-  for (int t = b.first; t < b.end; t += b.step) {
+  const TileBand b(c.em_end - c.em_begin);
+  for (int i = b.first; i < b.end; i += b.step) {
     __syncthreads();  // the previous tile's write-back has read the LDS
+    const int t = c.em_begin + i;
     const BatchViewK &bv = vs[batch_find<true>(vs, n_views, t)];
     const int l = t - bv.em_begin;
     const int tx0 = (l % bv.em_tiles_x) * TW, ty0 = (l / bv.em_tiles_x) * TH;

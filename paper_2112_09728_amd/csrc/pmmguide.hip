@@ -315,26 +315,46 @@ BatchViewK to_batch(const pg_batch_view &b, int rs_begin, int em_begin, Tile t) 
 }
 
 template <typename TG, int TW, int TH>
-pg_status launch_em_batched_t(const void *table, int dtype, int spp, hipStream_t st) {
+pg_status launch_em_batched_t(const void *table, int dtype, int cls, int spp, int n_tiles, hipStream_t st) {
   const size_t lds = tile_lds(Tile{TW, TH}, spp);
   int blocks = 0;
   pg_status e = persistent_blocks((const void *)k_em_batched<TG, TW, TH>, TW * TH, lds, blocks);
   if (e) return e;
+  if (blocks > n_tiles) blocks = n_tiles;
   hipLaunchKernelGGL((k_em_batched<TG, TW, TH>), dim3(blocks), dim3(TW * TH), lds, st, (const char *)table, dtype,
-                     spp);
+                     cls, spp);
   return PG_OK;
 }
 
 template <typename TG>
-pg_status launch_em_batched(Tile t, const void *table, int dtype, int spp, hipStream_t st) {
-  if (t.w == 32 && t.h == 8) return launch_em_batched_t<TG, 32, 8>(table, dtype, spp, st);
-  if (t.w == 16 && t.h == 16) return launch_em_batched_t<TG, 16, 16>(table, dtype, spp, st);
-  if (t.w == 64 && t.h == 4) return launch_em_batched_t<TG, 64, 4>(table, dtype, spp, st);
-  if (t.w == 32 && t.h == 4) return launch_em_batched_t<TG, 32, 4>(table, dtype, spp, st);
-  if (t.w == 16 && t.h == 8) return launch_em_batched_t<TG, 16, 8>(table, dtype, spp, st);
-  if (t.w == 32 && t.h == 16) return launch_em_batched_t<TG, 32, 16>(table, dtype, spp, st);
-  if (t.w == 64 && t.h == 8) return launch_em_batched_t<TG, 64, 8>(table, dtype, spp, st);
-  return launch_em_batched_t<TG, 64, 2>(table, dtype, spp, st);
+pg_status launch_em_batched(const BatchClass &c, const void *table, int dtype, int cls, hipStream_t st) {
+  const int n = c.em_end - c.em_begin;
+  const Tile t{c.tile_w, c.tile_h};
+  if (t.w == 32 && t.h == 8) return launch_em_batched_t<TG, 32, 8>(table, dtype, cls, c.spp, n, st);
+  if (t.w == 16 && t.h == 16) return launch_em_batched_t<TG, 16, 16>(table, dtype, cls, c.spp, n, st);
+  if (t.w == 64 && t.h == 4) return launch_em_batched_t<TG, 64, 4>(table, dtype, cls, c.spp, n, st);
+  if (t.w == 32 && t.h == 4) return launch_em_batched_t<TG, 32, 4>(table, dtype, cls, c.spp, n, st);
+  if (t.w == 16 && t.h == 8) return launch_em_batched_t<TG, 16, 8>(table, dtype, cls, c.spp, n, st);
+  if (t.w == 32 && t.h == 16) return launch_em_batched_t<TG, 32, 16>(table, dtype, cls, c.spp, n, st);
+  if (t.w == 64 && t.h == 8) return launch_em_batched_t<TG, 64, 8>(table, dtype, cls, c.spp, n, st);
+  return launch_em_batched_t<TG, 64, 2>(table, dtype, cls, c.spp, n, st);
+}
+
+// Training tile of a class of the batch: the requested one where its LDS
+// fits that spp, else the default for that spp.
+pg_status class_tile(const pg_params *p, int spp, Tile &t) {
+  if (p->tile_w == 0 && p->tile_h == 0) {
+    t = default_tile(spp);
+    return PG_OK;
+  }
+  pg_status st = pick_tile(p, spp, t);
+  if (st == PG_OK) return st;
+  bool built = false;
+  for (const Tile &c : kTiles)
+    if (c.w == p->tile_w && c.h == p->tile_h) built = true;
+  if (!built) return st;  // an unknown shape stays an error
+  t = default_tile(spp);
+  return ok();
 }
 
 }  // namespace
@@ -504,8 +524,8 @@ pg_status pg_batch_pack(const pg_batch_view *views, int32_t n_views, void *host_
   if (!host_table || bytes < batch_bytes(n_views))
     return fail(PG_ERR_ARG, "pg_batch_pack: table of %zu bytes, %zu needed", bytes, batch_bytes(n_views));
   const int dtype = views[0].gamma_out.dtype;
-  int max_spp = 0;
   pg_status st;
+  int per_spp[kMaxSpp + 1] = {0};
   for (int i = 0; i < n_views; ++i) {
     if ((st = in_view(check_batch_view(views[i], dtype), i))) return st;
     if (!shared_params_equal(views[i].params, views[0].params))
@@ -513,31 +533,49 @@ pg_status pg_batch_pack(const pg_batch_view *views, int32_t n_views, void *host_
     for (int j = 0; j < i; ++j)
       if (views[j].gamma_out.data == views[i].gamma_out.data || views[j].samples.dir == views[i].samples.dir)
         return in_view(fail(PG_ERR_ARG, "output buffers shared with view %d", j), i);
-    if (views[i].samples.spp > max_spp) max_spp = views[i].samples.spp;
+    ++per_spp[views[i].samples.spp];
   }
-  Tile t;
-  if ((st = pick_tile(&views[0].params, max_spp, t))) return st;
+  // classes by spp, each with its tile
+  BatchClass cls[kMaxSpp];
+  Tile ctile[kMaxSpp];
+  int n_classes = 0, class_of[kMaxSpp + 1];
+  for (int spp = 1; spp <= kMaxSpp; ++spp) {
+    class_of[spp] = -1;
+    if (!per_spp[spp]) continue;
+    if ((st = class_tile(&views[0].params, spp, ctile[n_classes]))) return st;
+    std::memset(&cls[n_classes], 0, sizeof(BatchClass));
+    cls[n_classes].spp = spp;
+    cls[n_classes].tile_w = ctile[n_classes].w;
+    cls[n_classes].tile_h = ctile[n_classes].h;
+    class_of[spp] = n_classes++;
+  }
   std::memset(host_table, 0, batch_bytes(n_views));
   BatchViewK *out = reinterpret_cast<BatchViewK *>((char *)host_table + kBatchViewsOffset);
   int64_t rs = 0, em = 0;
-  for (int i = 0; i < n_views; ++i) {
-    const pg_view &c = views[i].cur;
-    out[i] = to_batch(views[i], (int)rs, (int)em, t);
-    rs += (int64_t)((c.width + 63) / 64) * ((c.height + 3) / 4);
-    em += (int64_t)((c.width + t.w - 1) / t.w) * ((c.height + t.h - 1) / t.h);
-    if (rs >= ((int64_t)1 << 31) || em >= ((int64_t)1 << 31))
-      return fail(PG_ERR_UNSUPPORTED, "pg_batch_pack: too many tiles for 32-bit indexing");
+  int k = 0;
+  for (int c = 0; c < n_classes; ++c) {
+    cls[c].em_begin = (int)em;
+    for (int i = 0; i < n_views; ++i) {  // the views of this class in the caller's order
+      if (class_of[views[i].samples.spp] != c) continue;
+      const pg_view &cv = views[i].cur;
+      const Tile t = ctile[c];
+      out[k++] = to_batch(views[i], (int)rs, (int)em, t);
+      rs += (int64_t)((cv.width + 63) / 64) * ((cv.height + 3) / 4);
+      em += (int64_t)((cv.width + t.w - 1) / t.w) * ((cv.height + t.h - 1) / t.h);
+      if (rs >= ((int64_t)1 << 31) || em >= ((int64_t)1 << 31))
+        return fail(PG_ERR_UNSUPPORTED, "pg_batch_pack: too many tiles for 32-bit indexing");
+    }
+    cls[c].em_end = (int)em;
   }
   BatchHeader *hd = reinterpret_cast<BatchHeader *>(host_table);
   hd->n_views = n_views;
   hd->rs_tiles = (int)rs;
   hd->em_tiles = (int)em;
   hd->dtype = dtype;
-  hd->max_spp = max_spp;
-  hd->tile_w = t.w;
-  hd->tile_h = t.h;
-  hd->pad = kBatchMagic;
+  hd->n_classes = n_classes;
+  hd->magic = kBatchMagic;
   hd->base = to_k(&views[0].params);
+  for (int c = 0; c < n_classes; ++c) hd->cls[c] = cls[c];
   return ok();
 }
 
@@ -545,20 +583,22 @@ pg_status pg_frame_batched(const void *host_table, void *device_table, size_t by
   if (!host_table || !device_table) return fail(PG_ERR_ARG, "pg_frame_batched: NULL table");
   if (bytes < (size_t)kBatchViewsOffset) return fail(PG_ERR_ARG, "pg_frame_batched: table too small");
   const BatchHeader hd = *reinterpret_cast<const BatchHeader *>(host_table);
-  if (hd.pad != kBatchMagic || hd.n_views < 1 || bytes < batch_bytes(hd.n_views))
+  if (hd.magic != kBatchMagic || hd.n_views < 1 || bytes < batch_bytes(hd.n_views) || hd.n_classes < 1 ||
+      hd.n_classes > kMaxSpp)
     return fail(PG_ERR_ARG, "pg_frame_batched: host_table was not packed by pg_batch_pack for %zu bytes", bytes);
   hipStream_t s = (hipStream_t)stream;
   if (hipMemcpyAsync(device_table, host_table, batch_bytes(hd.n_views), hipMemcpyHostToDevice, s) != hipSuccess)
     return fail(PG_ERR_HIP, "pg_frame_batched: table upload failed: %s", hipGetErrorString(hipGetLastError()));
-  const Tile t{hd.tile_w, hd.tile_h};
   return dispatch_dtype(hd.dtype, [&](auto *tag) {
     using TG = std::remove_pointer_t<decltype(tag)>;
     int blocks = 0;
     pg_status e = persistent_blocks((const void *)k_rs_batched<TG>, 256, 0, blocks);
     if (e) return e;
+    if (blocks > hd.rs_tiles) blocks = hd.rs_tiles;
     hipLaunchKernelGGL((k_rs_batched<TG>), dim3(blocks), dim3(256), 0, s, (const char *)device_table, hd.dtype);
     if ((e = check_launch("pg_frame_batched (sampling)"))) return e;
-    if ((e = launch_em_batched<TG>(t, device_table, hd.dtype, hd.max_spp, s))) return e;
+    for (int c = 0; c < hd.n_classes; ++c)
+      if ((e = launch_em_batched<TG>(hd.cls[c], device_table, hd.dtype, c, s))) return e;
     return check_launch("pg_frame_batched (training)");
   });
 }

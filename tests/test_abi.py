@@ -158,17 +158,20 @@ def _pack(views, nbytes=None):
 
 def test_batch_pack_layout_and_tile_counts():
     """Host-only packing: the header counts the 64x4 sampling tiles and the
-    training tiles of every view, and takes the largest spp."""
-    sizes = [(70, 37, 1), (129, 64, 3), (33, 95, 8), (640, 360, 2)]
-    views = [_bview(w, h, spp, base=i << 16, tile_w=32, tile_h=4) for i, (w, h, spp) in enumerate(sizes)]
+    training tiles of every view (the requested tile where it fits the view's
+    spp) and groups the views by spp."""
+    sizes = [(70, 37, 1), (129, 64, 3), (33, 95, 8), (640, 360, 2), (40, 40, 3)]
+    views = [_bview(w, h, spp, base=i << 16, tile_w=32, tile_h=8) for i, (w, h, spp) in enumerate(sizes)]
     st, msg, table = _pack(views)
     assert st == pg.PG_OK, msg
-    hd = table[:32].view(torch.int32).tolist()
-    n, rs, em, dtype, max_spp, tw, th, magic = hd
-    assert (n, dtype, max_spp, tw, th) == (4, pg.PG_F32, 8, 32, 4)
+    n, rs, em, dtype, n_classes, magic = table[:24].view(torch.int32).tolist()
+    assert (n, dtype, n_classes, magic) == (5, pg.PG_F32, 4, 0x31424750)
     assert rs == sum(-(-w // 64) * -(-h // 4) for w, h, _ in sizes)
-    assert em == sum(-(-w // 32) * -(-h // 4) for w, h, _ in sizes)
-    assert magic == 0x31424750
+
+    def tiles(w, h, spp):  # 32x8 needs more than 64 KiB of LDS at spp 8: the default 32x4 there
+        tw, th = (32, 8) if spp <= 4 else (32, 4)
+        return -(-w // tw) * -(-h // th)
+    assert em == sum(tiles(*v) for v in sizes)
     assert pg.batch_table_bytes(0) == 0
     assert pg.batch_table_bytes(2) - pg.batch_table_bytes(1) == pg.batch_table_bytes(3) - pg.batch_table_bytes(2)
 
@@ -192,8 +195,8 @@ def test_batch_pack_rejects_bad_batches():
         (spp9, pg.PG_ERR_ARG, "view 0"),
         (no_albedo, pg.PG_ERR_ARG, "view 0"),
         ([_bview(flags=pg.PG_EM_BATCH)], pg.PG_ERR_UNSUPPORTED, "view 0"),
-        # 32x8 training tiles with 8 spp need more than 64 KiB of LDS
-        ([_bview(spp=8, tile_w=32, tile_h=8)], pg.PG_ERR_UNSUPPORTED, "LDS"),
+        # a tile shape that is not built
+        ([_bview(tile_w=24, tile_h=24)], pg.PG_ERR_UNSUPPORTED, "not built"),
     ]
     for views, want, where in cases:
         st, msg, _ = _pack(views)
