@@ -224,7 +224,8 @@ typedef struct pg_batch_view {
                           views of every spp whose LDS it fits, the default
                           tile of that spp elsewhere (0 = defaults)          */
   pg_view cur;         /* this frame's G-buffer (albedo required)             */
-  pg_view prev;        /* previous frame's (read when params.frame > 0)       */
+  pg_view prev;        /* previous frame's (read when params.frame > 0; same
+                          width, height and pitch as cur)                    */
   pg_gamma gamma_in;   /* previous state (read when params.frame > 0)         */
   pg_gamma gamma_out;  /* this frame's state, cur's height and pitch; must not
                           alias gamma_in; one dtype for all views             */

@@ -72,21 +72,39 @@ __device__ __forceinline__ Pixel make_pixel(const ParamsK &P, V3 n, V3 o, float 
 // into a source address or a reset flag use explicit operation orders:
 // validity and the normal test are fma(z, z', fma(y, y', x * x')), the
 // address is (x + 1/2) - mv, the depth test |z - z'| > tau z.
+// The G-buffer values of one pixel that both reprojection and sampling read.
+struct PixelIn {
+  V3 n, o;
+  float rough;
+};
+
+__device__ __forceinline__ PixelIn load_pixel(const ViewK &v, int idx) {
+  const int plane = v.H * v.pitch;
+  return PixelIn{load3(v.n, plane, idx), load3(v.o, plane, idx), v.rough[idx]};
+}
+
 template <typename TG>
 __device__ __forceinline__ int reproject_pixel(const ParamsK &P, const ViewK &cur, const ViewK &prev,
                                                const TG *__restrict__ gprev, bool has_prev, int x,
-                                               int y, float g[8]) {
+                                               int y, const PixelIn &pi, float g[8]) {
   const int plane = cur.H * cur.pitch;
   const int idx = y * cur.pitch + x;
-  const V3 n = load3(cur.n, plane, idx);
-  const V3 o = load3(cur.o, plane, idx);
-  const bool guided = dot3(n, o) > 0.0f && cur.rough[idx] >= P.rough_min;
+  const V3 n = pi.n;
+  const bool guided = dot3(n, pi.o) > 0.0f && pi.rough >= P.rough_min;
+  // everything read at p, then everything read at the source q: two rounds
+  // of loads whatever the tests decide
+  float zp = 0.0f, mx = 0.0f, my = 0.0f;
   bool keep = has_prev && guided;
-  if (keep && cur.mask != nullptr && cur.mask[idx] != 0) keep = false;
+  if (keep) {
+    zp = cur.z[idx];
+    if (cur.mv) {
+      mx = cur.mv[idx];
+      my = cur.mv[plane + idx];
+    }
+    if (cur.mask != nullptr && cur.mask[idx] != 0) keep = false;
+  }
   int qx = 0, qy = 0;
   if (keep) {
-    const float mx = cur.mv ? cur.mv[idx] : 0.0f;
-    const float my = cur.mv ? cur.mv[plane + idx] : 0.0f;
     const float fx = ((float)x + 0.5f) - mx;
     const float fy = ((float)y + 0.5f) - my;
     if (fx >= 0.0f && fy >= 0.0f && fx < (float)prev.W && fy < (float)prev.H) {
@@ -99,16 +117,14 @@ __device__ __forceinline__ int reproject_pixel(const ParamsK &P, const ViewK &cu
   if (keep) {
     const int pplane = prev.H * prev.pitch;
     const int qidx = qy * prev.pitch + qx;
-    const float zp = cur.z[idx], zq = prev.z[qidx];
-    if (fabsf(zp - zq) > P.tau_z * zp) keep = false;
+    const float zq = prev.z[qidx];
     const V3 nq = load3(prev.n, pplane, qidx);
+    gamma_load(gprev, pplane, qidx, g);
+    if (fabsf(zp - zq) > P.tau_z * zp) keep = false;
     if (dot3(n, nq) < P.tau_n) keep = false;
-    if (keep) {
-      gamma_load(gprev, pplane, qidx, g);
 #pragma unroll
-      for (int c = 0; c < 8; ++c)
-        if (!isfinite(g[c])) keep = false;
-    }
+    for (int c = 0; c < 8; ++c)
+      if (!isfinite(g[c])) keep = false;
     if (keep && !(n.x == nq.x && n.y == nq.y && n.z == nq.z)) {
       // change of hemisphere: keep the world direction of M(mu)
       const Frame fq = make_frame(nq);
@@ -155,14 +171,13 @@ __device__ __forceinline__ float light_radiance(const LightsK &Lt, uint32_t bits
 // With Lt given, the radiance of each sample is evaluated as well (the
 // batched frame fuses the trace stand-in into this pass).
 __device__ __forceinline__ void sample_pixel(const ParamsK &P, const ViewK &v, const SamplesK &S,
-                                             int x, int y, const float g[8], const LightsK *Lt = nullptr,
-                                             uint32_t visbits = 0) {
+                                             int x, int y, const PixelIn &pi, const float g[8],
+                                             const LightsK *Lt = nullptr, uint32_t visbits = 0) {
   const int plane = v.H * v.pitch;
-  const int idx = y * v.pitch + x;
   const int splane = S.spp * plane;
-  const V3 n = load3(v.n, plane, idx);
-  const V3 o = load3(v.o, plane, idx);
-  const float rough = v.rough[idx];
+  const V3 n = pi.n;
+  const V3 o = pi.o;
+  const float rough = pi.rough;
   const bool valid = dot3(n, o) > 0.0f;
   const bool guided = valid && rough >= P.rough_min;
   const float pe = (guided && g[7] >= 1.0f) ? g[5] : 0.0f;
@@ -257,8 +272,8 @@ __global__ __launch_bounds__(256) void k_reproject(ParamsK P, ViewK cur, ViewK p
   const int y = blockIdx.y * 4 + threadIdx.y;
   if (x >= cur.W || y >= cur.H) return;
   float g[8];
-  const int src = reproject_pixel(P, cur, prev, gprev, has_prev != 0, x, y, g);
   const int idx = y * cur.pitch + x;
+  const int src = reproject_pixel(P, cur, prev, gprev, has_prev != 0, x, y, load_pixel(cur, idx), g);
   gamma_store(gout, cur.H * cur.pitch, idx, g);
   if (src_index) src_index[idx] = src;
 }
@@ -270,12 +285,36 @@ __global__ __launch_bounds__(256) void k_sample(ParamsK P, ViewK v, const TG *__
   const int y = blockIdx.y * 4 + threadIdx.y;
   if (x >= v.W || y >= v.H) return;
   float g[8];
-  gamma_load(gamma, v.H * v.pitch, y * v.pitch + x, g);
-  sample_pixel(P, v, S, x, y, g);
+  const int idx = y * v.pitch + x;
+  gamma_load(gamma, v.H * v.pitch, idx, g);
+  sample_pixel(P, v, S, x, y, load_pixel(v, idx), g);
 }
 
-// Reprojection and sampling fused: the reprojected model stays in registers.
-// The sample pass sees the state exactly as stored (rounded to TG).
+// Reprojection and sampling of one pixel: the reprojected model stays in
+// registers, the sample pass sees it exactly as stored (rounded to TG), and
+// the state is stored last (after the G-buffer has been read once).
+template <typename TG>
+__device__ __forceinline__ void reproject_sample_pixel(const ParamsK &P, const ViewK &cur, const ViewK &prev,
+                                                       const TG *__restrict__ gprev, TG *__restrict__ gout,
+                                                       const SamplesK &S, bool has_prev, int x, int y,
+                                                       const LightsK *Lt = nullptr,
+                                                       const uint8_t *vis = nullptr) {
+  const int idx = y * cur.pitch + x;
+  const PixelIn pi = load_pixel(cur, idx);
+  const uint32_t visbits = vis ? vis[idx] : 0u;
+  float g[8];
+  reproject_pixel(P, cur, prev, gprev, has_prev, x, y, pi, g);
+  float gs[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    TG t;
+    GammaIO<TG>::store(&t, c == 6 ? fminf(g[c], GammaIO<TG>::kMax) : g[c]);
+    gs[c] = GammaIO<TG>::load(&t);
+  }
+  sample_pixel(P, cur, S, x, y, pi, gs, Lt, visbits);
+  gamma_store(gout, cur.H * cur.pitch, idx, g);
+}
+
 template <typename TG>
 __global__ __launch_bounds__(256) void k_reproject_sample(ParamsK P, ViewK cur, ViewK prev,
                                                           const TG *__restrict__ gprev,
@@ -284,19 +323,7 @@ __global__ __launch_bounds__(256) void k_reproject_sample(ParamsK P, ViewK cur, 
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int y = blockIdx.y * 4 + threadIdx.y;
   if (x >= cur.W || y >= cur.H) return;
-  float g[8];
-  reproject_pixel(P, cur, prev, gprev, has_prev != 0, x, y, g);
-  const int idx = y * cur.pitch + x;
-  const int plane = cur.H * cur.pitch;
-  gamma_store(gout, plane, idx, g);
-  float gs[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    TG t;
-    GammaIO<TG>::store(&t, c == 6 ? fminf(g[c], GammaIO<TG>::kMax) : g[c]);
-    gs[c] = GammaIO<TG>::load(&t);
-  }
-  sample_pixel(P, cur, S, x, y, gs);
+  reproject_sample_pixel(P, cur, prev, gprev, gout, S, has_prev != 0, x, y);
 }
 
 // Densities of given directions.
@@ -977,20 +1004,8 @@ __global__ __launch_bounds__(256) void k_rs_batched(const char *__restrict__ tab
     ViewK prev = cur;
     prev.n = bv.prev_n;
     prev.z = bv.prev_z;
-    const bool has_prev = bv.frame > 0;
-    float g[8];
-    reproject_pixel(P, cur, prev, (const TG *)bv.gprev, has_prev, x, y, g);
-    const int idx = y * cur.pitch + x;
-    gamma_store((TG *)bv.gout, cur.H * cur.pitch, idx, g);
-    // sample from the state as stored
-    float gs[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      TG q;
-      GammaIO<TG>::store(&q, c == 6 ? fminf(g[c], GammaIO<TG>::kMax) : g[c]);
-      gs[c] = GammaIO<TG>::load(&q);
-    }
-    sample_pixel(P, cur, bv.S, x, y, gs, &bv.lights, bv.vis[idx]);
+    reproject_sample_pixel(P, cur, prev, (const TG *)bv.gprev, (TG *)bv.gout, bv.S, bv.frame > 0, x, y,
+                           &bv.lights, bv.vis);
   }
 }
 

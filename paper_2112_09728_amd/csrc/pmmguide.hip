@@ -284,6 +284,8 @@ pg_status check_batch_view(const pg_batch_view &b, int dtype) {
   if (b.gamma_out.dtype != dtype) return fail(PG_ERR_ARG, "views store Gamma in different dtypes");
   if (b.params.frame > 0) {
     if ((st = check_view(&b.prev, "prev", false)) || (st = check_gamma(b.gamma_in, "gamma_in"))) return st;
+    if (b.prev.width != b.cur.width || b.prev.height != b.cur.height || b.prev.pitch != b.cur.pitch)
+      return fail(PG_ERR_UNSUPPORTED, "the batched frame needs prev and cur of one size and pitch");
     if (b.gamma_in.dtype != dtype) return fail(PG_ERR_ARG, "gamma_in and gamma_out dtypes differ");
     if (b.gamma_in.data == b.gamma_out.data) return fail(PG_ERR_ARG, "gamma_in aliases gamma_out");
   }

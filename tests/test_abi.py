@@ -187,6 +187,8 @@ def test_batch_pack_rejects_bad_batches():
     spp9 = [_bview(spp=9)]
     no_albedo = [_bview()]
     no_albedo[0].cur = _view(albedo=False)
+    prev_size = [_bview()]
+    prev_size[0].prev = _view(w=9)
     cases = [
         (bad_dtype, pg.PG_ERR_ARG, "view 1"),
         (shared_out, pg.PG_ERR_ARG, "view 1"),
@@ -194,6 +196,7 @@ def test_batch_pack_rejects_bad_batches():
         (params_differ, pg.PG_ERR_ARG, "view 1"),
         (spp9, pg.PG_ERR_ARG, "view 0"),
         (no_albedo, pg.PG_ERR_ARG, "view 0"),
+        (prev_size, pg.PG_ERR_UNSUPPORTED, "view 0"),
         ([_bview(flags=pg.PG_EM_BATCH)], pg.PG_ERR_UNSUPPORTED, "view 0"),
         # a tile shape that is not built
         ([_bview(tile_w=24, tile_h=24)], pg.PG_ERR_UNSUPPORTED, "not built"),
