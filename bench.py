@@ -46,6 +46,36 @@ def bytes_light(S):
     return 1 + 17 * S
 
 
+VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9  # 256 CUs x 4 SIMDs x 16 lanes per clock at 2.4 GHz
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash():
+    """sha256 prefix of the HIP sources, as recorded in the profile summaries."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2112_09728_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profile_row(name, kernel):
+    """The table row of `kernel` in profiles/<name>, as a list of cells, if
+    the summary was taken on the current kernel sources (else None)."""
+    path = os.path.join(PROFILES, name)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if f"`{kernel_source_hash()}`" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("|") and (f"::{kernel}<" in line or f"::{kernel}`" in line):
+            return [c.strip() for c in line.strip("|").split("|")]
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +193,24 @@ def main():
     path_gbs = b_path * px / (ms * 1e-3) / 1e9
     dominant = "em" if em.mean() >= rs.mean() else "reproject_sample"
     dom_gbs, dom_bytes = (em_gbs, b_em) if dominant == "em" else (rs_gbs, b_rs)
+    # measured HBM traffic and VALU counts of the dominant kernel, from the
+    # committed rocprofv3 summaries of this workload (null when the kernel
+    # sources have changed since, or for another workload)
+    default = (W, H, S, a.gamma_dtype, a.tile, a.unfused) == (1920, 1080, 1, "f32", None, False)
+    dom_name = "k_em" if dominant == "em" else "k_reproject_sample"
+    traffic = alu = None
+    if default:
+        row = profile_row("path_1080p_spp1_pan_traffic.md", dom_name)
+        if row:
+            traffic = round((float(row[3]) + float(row[4])) * 1e6)
+        row = profile_row("path_1080p_spp1_pan_sq_counters.md", dom_name)
+        if row:
+            lane_ops = float(row[1]) * float(row[2]) * 64
+            us = float((em if dominant == "em" else rs).mean()) * 1e3
+            ach = lane_ops / (us * 1e-6)
+            alu = {"bound": "alu", "kernel": dom_name, "quantity": "issued VALU lane-ops (rocprofv3 SQ_INSTS_VALU x 64)",
+                   "achieved": round(ach / 1e12, 2), "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2), "unit": "T lane-op/s",
+                   "frac": round(ach / VALU_PEAK_LANE_OPS, 4), "valu_per_wave": float(row[2])}
     gk = guide.state
     kmean = float(gk[7].float().mean())
     print(f"bench: per frame reproject+sample {rs.mean() * 1e3:.1f} us, light {lf.mean() * 1e3:.1f} us, "
@@ -200,7 +248,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
             "bytes_per_px": dom_bytes,
             "us_per_launch": round(float((em if dominant == "em" else rs).mean()) * 1e3, 2),
         },
@@ -212,6 +260,7 @@ def main():
             "em_us": round(float(em.mean()) * 1e3, 2),
             "light_field_us": round(float(lf.mean()) * 1e3, 2),
         },
+        "alu_roofline": alu,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
