@@ -408,3 +408,35 @@ def test_pan_sequence_reprojects_onto_the_same_surface():
     qy, qx = np.divmod(src[src >= 0], W)
     same = (f0["roughness"][qy, qx] == f1["roughness"][src >= 0])
     assert same.mean() > 0.9
+
+
+def test_dependency_cone_reproduces_the_full_frame_run():
+    """Gamma_t on a crop depends on Gamma_{t-1} within 5 px (2 px of motion, 3
+    px of picks): stepping the crop grown by 5 px per remaining frame (the
+    full-size GPU tests free-run their crops this way) equals the full-frame
+    run on the crop exactly."""
+    import sys as _sys
+    import os as _os
+    _sys.path.insert(0, _os.path.dirname(__file__))
+    from test_gpu_configs import OracleCone
+    W, H, seed, crop, n = 160, 120, 77, (48, 40, 112, 88), 5
+    seq, seq_full = wl.Sequence(W, H, seed), wl.Sequence(W, H, seed)
+    cone = OracleCone(seed, 1, crop, n, W, H)
+    full = O.Frames(seed=seed, spp=1)
+    for t in range(n):
+        cone.step(t, seq.frame(t))
+        full.step(t, seq_full.frame(t))
+    x0, y0, x1, y1 = crop
+    assert np.array_equal(cone.gamma[:, y0:y1, x0:x1], full.gamma[:, y0:y1, x0:x1])
+    # and a cone one pixel too narrow does not (the reading is tight)
+    narrow = OracleCone(seed, 1, crop, n, W, H)
+    import test_gpu_configs as _cfg
+    old = _cfg.CONE
+    _cfg.CONE = 4
+    try:
+        seq = wl.Sequence(W, H, seed)
+        for t in range(n):
+            narrow.step(t, seq.frame(t))
+    finally:
+        _cfg.CONE = old
+    assert not np.array_equal(narrow.gamma[:, y0:y1, x0:x1], full.gamma[:, y0:y1, x0:x1])
