@@ -582,7 +582,7 @@ __device__ __forceinline__ int build_list(const ParamsK &P, const float4 *lds, u
 constexpr int kMaxLen = kMaxSpp + 21;
 
 template <int NT>
-__device__ __forceinline__ int balance(int len, int item, int *cnt, int *perm, int rot) {
+__device__ __forceinline__ int balance(int len, int item, int *cnt, uint16_t *perm, int rot) {
   static_assert(kMaxLen <= 32, "one half-wave scans the classes");
   const int rank = atomicAdd(&cnt[len], 1);
   __syncthreads();
@@ -602,7 +602,7 @@ __device__ __forceinline__ int balance(int len, int item, int *cnt, int *perm, i
   constexpr int NW = NT / 64;
   const int pos = cnt[len] + rank;                                // rank in the sorted order
   const int wave = NW > 1 ? ((pos >> 6) + rot) % NW : 0;
-  perm[wave * 64 + (pos & 63)] = item;
+  perm[wave * 64 + (pos & 63)] = (uint16_t)item;
   __syncthreads();
   return perm[threadIdx.x];
 }
@@ -611,7 +611,7 @@ __device__ __forceinline__ int balance(int len, int item, int *cnt, int *perm, i
 template <int NT>
 struct EmShared {
   int cnt[2][kMaxLen];
-  int perm[NT];
+  uint16_t perm[NT];
   uint8_t work[NT];  // per pixel: candidate count, then list length
 };
 
@@ -813,7 +813,7 @@ struct TileBand {
 // loads of one block behind the arithmetic of the others better than a
 // persistent loop with register prefetch.
 template <typename TG, int TW, int TH>
-__global__ __launch_bounds__(TW *TH) void k_em(ParamsK P, ViewK v, SamplesK S, TG *__restrict__ gamma,
+__global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(8))) void k_em(ParamsK P, ViewK v, SamplesK S, TG *__restrict__ gamma,
                                                int iterations, int batch, int tiles_x, int n_tiles) {
   extern __shared__ float4 lds[];  // records, state and lists (see em_tile)
   __shared__ EmShared<TW * TH> sh;
