@@ -209,6 +209,15 @@ pg_status pg_nll_backward(const pg_params *p, const pg_view *v, const pg_samples
                           const float *theta, const float *grad_out, float *grad_theta,
                           float *nll, void *stream);
 
+/* First-bounce estimate (the Monte Carlo estimator of the reflected radiance
+ * of Eq. (1) with the sampling density D of Eq. (2)): estimate [H*pitch]
+ * receives, per pixel, the mean over its samples of f_r(w) L(w) cos / D(w),
+ * where a null sample (strategy 0, 3 or 4) or D = 0 counts zero, and 0 for a
+ * pixel with omega_o below the surface.  Reads samples->dir, pdf_mix,
+ * strategy and radiance and the view's normal, view_dir, roughness, albedo. */
+pg_status pg_estimate(const pg_params *p, const pg_view *v, const pg_samples *in, float *estimate,
+                      void *stream);
+
 /* ---- Batched frame: many views in two persistent launches ----------------
  * One frame of n views of any size and spp (Sec. 3.1 and Sec. 3.2 for each
  * view, with the light-field stand-in between them) as an upload of a packed

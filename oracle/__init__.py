@@ -81,6 +81,8 @@ def _declare(L):
     L.orc_light.argtypes = [i32, P, C.c_double, P, i32, i32, i32, i32, P, P, P, Rect]
     L.orc_em.argtypes = [P, P, i32, P, P, P, P, P, i32, i32, P, Rect]
     L.orc_nll.argtypes = [P, P, i32, P, P, P, P, P, P, P, P, Rect]
+    L.orc_estimate.argtypes = [P, P, i32, P, P, P, P, P, Rect]
+    L.orc_reference.argtypes = [P, P, i32, P, C.c_double, P, i32, i64, P, P, P]
     L.orc_num_threads.restype = i32
 
 
@@ -295,6 +297,31 @@ def em(P, view, rec, gamma, iterations=1, batch=False, rect=None, with_stats=Fal
     lib().orc_em(C.byref(P), C.byref(view.c), spp, _ptr(d), _ptr(pb), _ptr(st), _ptr(L), _ptr(g),
                  iterations, int(bool(batch)), _ptr(stats), _rect(view, rect))
     return (g, stats) if with_stats else g
+
+
+def estimate(P, view, rec, rect=None):
+    """Per-pixel mean of f_r L cos / D over the records' samples [H][W]."""
+    spp = rec["strategy"].shape[0]
+    d, pm = _f64(rec["dir"]), _f64(rec["pdf_mix"])
+    st = np.ascontiguousarray(rec["strategy"], dtype=np.uint8)
+    L = _f64(rec["radiance"])
+    out = np.zeros((view.height, view.width))
+    lib().orc_estimate(C.byref(P), C.byref(view.c), spp, _ptr(d), _ptr(pm), _ptr(st), _ptr(L), _ptr(out),
+                       _rect(view, rect))
+    return out
+
+
+def reference(P, view, lights, ambient, vis, pixels, n_samples=16384):
+    """Reference int f_r L cos for flat pixel indices `pixels` (y*W + x):
+    (mean, standard error) arrays."""
+    lights = _f32(lights)
+    vis = np.ascontiguousarray(vis, dtype=np.uint8)
+    idx = np.ascontiguousarray(pixels, dtype=np.int64)
+    mean = np.zeros(idx.shape[0])
+    se = np.zeros(idx.shape[0])
+    lib().orc_reference(C.byref(P), C.byref(view.c), lights.shape[0], _ptr(lights), float(ambient), _ptr(vis),
+                        int(n_samples), idx.shape[0], _ptr(idx), _ptr(mean), _ptr(se))
+    return mean, se
 
 
 def nll(P, view, rec, theta, grad_out=None, rect=None):

@@ -934,6 +934,124 @@ void orc_nll(const orc_params *P, const orc_view *v, int32_t spp, const double *
   }
 }
 
+/* ------------------------------------------------------------------------- */
+/* The first-bounce estimator the guided samples feed (Eq. (1) estimated by
+ * Monte Carlo with the density D of Eq. (2)): per pixel the mean over its
+ * samples of f_r(w) L(w) cos(theta) / D(w), a null sample (strategy 0, 3 or
+ * 4) contributing zero.  Pixels with omega_o below the surface give 0. */
+void orc_estimate(const orc_params *P, const orc_view *v, int32_t spp, const double *dir,
+                  const double *pdf_mix, const uint8_t *strategy, const double *radiance, double *out,
+                  orc_rect r) {
+  const int64_t pl = (int64_t)v->height * v->pitch;
+  const int64_t spl = (int64_t)spp * pl;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int y = r.y0; y < r.y1; ++y) {
+    for (int x = r.x0; x < r.x1; ++x) {
+      const int64_t idx = (int64_t)y * v->pitch + x;
+      const pixel_t px = load_pixel(P, v, idx);
+      double acc = 0.0;
+      if (px.valid) {
+        for (int s = 0; s < spp; ++s) {
+          const int64_t o = (int64_t)s * pl + idx;
+          if (!(strategy[o] == 1 || strategy[o] == 2) || !(pdf_mix[o] > 0.0)) continue;
+          double w[3] = {dir[o], dir[spl + o], dir[2 * spl + o]}, l[3];
+          normalize3(w);
+          to_local(&px.f, w, l);
+          if (l[2] <= 0.0) continue;
+          acc += brdf_f(px.wo, l, px.alpha, px.albedo, (double)P->f0) * radiance[o] * l[2] / pdf_mix[o];
+        }
+        acc /= spp;
+      }
+      out[idx] = acc;
+    }
+  }
+}
+
+/* Reference value of the same integral, L_o = int f_r L cos dw over the upper
+ * hemisphere, for a list of pixels: Monte Carlo in FP64 with n samples per
+ * pixel drawn from the equal mixture of BRDF sampling and sampling of each
+ * visible spherical-Gaussian light lobe (balance heuristic: every sample is
+ * weighted by the mixture density).  An SG lobe exp(lambda (w.xi - 1)) is
+ * sampled exactly: cos = 1 + ln(u + (1 - u) e^(-2 lambda)) / lambda about xi,
+ * with density lambda exp(lambda (w.xi - 1)) / (2 pi (1 - e^(-2 lambda))).
+ * Random words: Philox4x32-10 with counter (pixel, frame, 7 * 2^16 + sample,
+ * view), one call per sample.  Returns the mean and its standard error. */
+static double sg_pdf(const double w[3], const double ax[3], double lambda) {
+  return lambda * exp(lambda * (dot3(w, ax) - 1.0)) / (2.0 * PI * (1.0 - exp(-2.0 * lambda)));
+}
+
+void orc_reference(const orc_params *P, const orc_view *v, int32_t n_lights, const float *lights,
+                   double ambient, const uint8_t *vis, int32_t n_samples, int64_t n_px, const int64_t *px_index,
+                   double *mean, double *stderr_out) {
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n_px; ++i) {
+    const int64_t idx = px_index[i];
+    const int64_t y = idx / v->pitch, x = idx % v->pitch;
+    const pixel_t px = load_pixel(P, v, idx);
+    if (!px.valid) {
+      mean[i] = 0.0;
+      stderr_out[i] = 0.0;
+      continue;
+    }
+    double ax[8][3], lam[8], cl[8];
+    int m = 0;
+    for (int k = 0; k < n_lights && k < 8; ++k) {
+      if (!((vis[idx] >> k) & 1u)) continue;
+      const float *lt = lights + 5 * k;
+      ax[m][0] = lt[0]; ax[m][1] = lt[1]; ax[m][2] = lt[2];
+      normalize3(ax[m]);
+      lam[m] = lt[3];
+      cl[m] = lt[4];
+      ++m;
+    }
+    const int J = 1 + m;
+    double s1 = 0.0, s2 = 0.0;
+    for (int n = 0; n < n_samples; ++n) {
+      uint32_t wds[4];
+      rng_words(P, (uint32_t)(y * v->width + x), 7u, (uint32_t)n, wds);
+      const double u0 = uniform24(wds[0]), u1 = uniform24(wds[1]), u2 = uniform24(wds[2]),
+                   u3 = uniform24(wds[3]);
+      int j = (int)(u0 * J);
+      if (j >= J) j = J - 1;
+      double l[3], w[3];
+      int ok = 1;
+      if (j == 0) {
+        ok = brdf_sample(px.wo, px.alpha, (double)P->s_diffuse, u1, u2, u3, l, NULL);
+        if (ok) {
+          normalize3(l);
+          to_world(&px.f, l, w);
+        }
+      } else {
+        const int k = j - 1;
+        const double c = 1.0 + log(u1 + (1.0 - u1) * exp(-2.0 * lam[k])) / lam[k];
+        const double sn = sqrt(fmax(0.0, 1.0 - c * c)), phi = 2.0 * PI * u2;
+        double t[3], b[3];
+        onb(ax[k], t, b);
+        for (int q = 0; q < 3; ++q) w[q] = c * ax[k][q] + sn * (cos(phi) * t[q] + sin(phi) * b[q]);
+        normalize3(w);
+        to_local(&px.f, w, l);
+        ok = l[2] > 0.0;
+      }
+      double val = 0.0;
+      if (ok && l[2] > 0.0) {
+        double q = brdf_pdf(px.wo, l, px.alpha, (double)P->s_diffuse);
+        double L = ambient;
+        for (int k = 0; k < m; ++k) {
+          q += sg_pdf(w, ax[k], lam[k]);
+          L += cl[k] * exp(lam[k] * (dot3(w, ax[k]) - 1.0));
+        }
+        q /= J;
+        if (q > 0.0) val = brdf_f(px.wo, l, px.alpha, px.albedo, (double)P->f0) * L * l[2] / q;
+      }
+      s1 += val;
+      s2 += val * val;
+    }
+    const double mu = s1 / n_samples;
+    mean[i] = mu;
+    stderr_out[i] = sqrt(fmax(0.0, s2 / n_samples - mu * mu) / n_samples);
+  }
+}
+
 int32_t orc_num_threads(void) {
 #ifdef _OPENMP
   return (int32_t)omp_get_max_threads();

@@ -115,6 +115,17 @@ void orc_nll(const orc_params *P, const orc_view *v, int32_t spp, const double *
              const double *pdf_brdf, const uint8_t *strategy, const double *radiance,
              const double *theta, const double *grad_out, double *grad, double *nll,
              orc_rect r);
+/* First-bounce estimate per pixel: mean over samples of f_r L cos / D
+ * (null samples contribute zero). */
+void orc_estimate(const orc_params *P, const orc_view *v, int32_t spp, const double *dir,
+                  const double *pdf_mix, const uint8_t *strategy, const double *radiance, double *out,
+                  orc_rect r);
+/* Reference value of int f_r L cos over the hemisphere for listed pixels
+ * (flat indices y*pitch + x): FP64 Monte Carlo with n_samples per pixel from
+ * the mixture of BRDF and light-lobe sampling; mean and standard error. */
+void orc_reference(const orc_params *P, const orc_view *v, int32_t n_lights, const float *lights,
+                   double ambient, const uint8_t *vis, int32_t n_samples, int64_t n_px, const int64_t *px_index,
+                   double *mean, double *stderr_out);
 int32_t orc_num_threads(void);
 
 #ifdef __cplusplus

@@ -64,7 +64,7 @@ class PgBatchView(C.Structure):
 
 
 EXPORTS = ("pg_params_default", "pg_reproject", "pg_sample_mis", "pg_reproject_sample", "pg_pdf",
-           "pg_light_field", "pg_em_update", "pg_nll_backward", "pg_batch_table_bytes",
+           "pg_light_field", "pg_em_update", "pg_nll_backward", "pg_estimate", "pg_batch_table_bytes",
            "pg_batch_pack", "pg_frame_batched", "pg_philox", "pg_last_error")
 
 _lib = None
@@ -91,6 +91,7 @@ def lib():
         L.pg_light_field.argtypes = [P, P, P, P, P]
         L.pg_em_update.argtypes = [P, P, P, PgGamma, C.c_int32, P]
         L.pg_nll_backward.argtypes = [P, P, P, P, P, P, P, P]
+        L.pg_estimate.argtypes = [P, P, P, P, P]
         L.pg_batch_table_bytes.argtypes = [C.c_int32]
         L.pg_batch_pack.argtypes = [P, C.c_int32, P, C.c_size_t]
         L.pg_frame_batched.argtypes = [P, P, C.c_size_t, P]
@@ -294,6 +295,15 @@ def nll_backward(p: PgParams, view: View, samples: Samples, theta, grad_out=None
                                  _ptr(grad_out), _ptr(grad), _ptr(nll), _stream()),
            "pg_nll_backward")
     return nll, grad
+
+
+def estimate(p: PgParams, view: View, samples: Samples):
+    """Per-pixel first-bounce estimate: mean of f_r L cos / D over the samples [H][W]."""
+    import torch
+    out = torch.empty((view.height, view.width), dtype=torch.float32, device=samples.dir.device)
+    _check(lib().pg_estimate(C.byref(p), C.byref(view.c), C.byref(samples.c), _ptr(out), _stream()),
+           "pg_estimate")
+    return out
 
 
 def batch_table_bytes(n_views: int) -> int:

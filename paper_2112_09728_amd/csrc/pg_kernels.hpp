@@ -145,6 +145,36 @@ __device__ __forceinline__ int reproject_pixel(const ParamsK &P, const ViewK &cu
   return qy * prev.W + qx;
 }
 
+// First-bounce estimate of one pixel: the mean over its samples of
+// f_r L cos / D (null samples count zero), the Monte Carlo estimator of the
+// reflected radiance with the mixture density of the samples.
+__global__ __launch_bounds__(256) void k_estimate(ParamsK P, ViewK v, SamplesK S, float *__restrict__ out) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  if (x >= v.W || y >= v.H) return;
+  const int plane = v.H * v.pitch;
+  const int idx = y * v.pitch + x;
+  const int splane = S.spp * plane;
+  const V3 n = load3(v.n, plane, idx), o = load3(v.o, plane, idx);
+  float acc = 0.0f;
+  if (dot3(n, o) > 0.0f) {
+    const Pixel px = make_pixel(P, n, o, v.rough[idx], v.alb[idx]);
+    for (int s = 0; s < S.spp; ++s) {
+      const int r = (s * v.H + y) * v.pitch + x;
+      const uint8_t code = S.strat[r];
+      const float D = S.pmix[r];
+      if (!(code == 1 || code == 2) || !(D > 0.0f)) continue;
+      const V3 l = to_local(px.f, normalized(V3{S.dir[r], S.dir[splane + r], S.dir[2 * splane + r]}));
+      if (l.z <= 0.0f) continue;
+      float f, pb;
+      brdf_eval(px, l, f, pb);
+      acc += f * S.L[r] * l.z / D;
+    }
+    acc /= (float)S.spp;
+  }
+  out[idx] = acc;
+}
+
 // Analytic incident radiance (stand-in for the trace).  For unit w and xi,
 // w . xi - 1 = -|w - xi|^2 / 2, which has no cancellation near the axis.
 struct LightsK {

@@ -518,6 +518,18 @@ pg_status pg_nll_backward(const pg_params *p, const pg_view *v, const pg_samples
   return check_launch("pg_nll_backward");
 }
 
+pg_status pg_estimate(const pg_params *p, const pg_view *v, const pg_samples *in, float *estimate, void *stream) {
+  pg_status st;
+  if ((st = check_params(p)) || (st = check_view(v, "view", true)) || (st = check_samples(in, true, true)))
+    return st;
+  if (!estimate) return fail(PG_ERR_ARG, "estimate is NULL");
+  const ParamsK P = to_k(p);
+  const ViewK V = to_k(v);
+  const SamplesK S = to_k(in);
+  hipLaunchKernelGGL(k_estimate, stream_grid(V.W, V.H), dim3(64, 4), 0, (hipStream_t)stream, P, V, S, estimate);
+  return check_launch("pg_estimate");
+}
+
 size_t pg_batch_table_bytes(int32_t n_views) { return n_views < 1 ? 0 : batch_bytes(n_views); }
 
 pg_status pg_batch_pack(const pg_batch_view *views, int32_t n_views, void *host_table, size_t bytes) {

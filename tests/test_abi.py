@@ -94,6 +94,10 @@ def test_argument_errors_before_launch():
          pg.PG_ERR_ARG),
         (L.pg_nll_backward, (C.byref(P), C.byref(v), C.byref(s), FAKE, None, None, None, None),
          pg.PG_ERR_ARG),
+        (L.pg_estimate, (C.byref(P), C.byref(v), C.byref(s), None, None), pg.PG_ERR_ARG),
+        (L.pg_estimate, (C.byref(P), C.byref(_view(albedo=False)), C.byref(s), FAKE, None), pg.PG_ERR_ARG),
+        (L.pg_estimate, (C.byref(P), C.byref(v), C.byref(_samples(radiance=False)), FAKE, None),
+         pg.PG_ERR_ARG),
         (L.pg_philox, (-1, None, 0, None, None), pg.PG_ERR_ARG),
     ]
     for fn, args, want in cases:
