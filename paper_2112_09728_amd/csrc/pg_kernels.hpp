@@ -36,6 +36,26 @@ constexpr int kR = 3;                       // pick radius: 7x7 window
 constexpr int kSide = 2 * kR + 1;
 constexpr int kCand = kSide * kSide - 1;    // 48 neighbours
 
+// Blocks are dealt to the 8 XCDs round robin; xcd_tile gives XCD j the j-th
+// contiguous run of the n tiles, so that neighbouring tiles (which share
+// cache lines and halos) are fetched into the same L2.
+__device__ __forceinline__ int xcd_tile(int bid, int n) {
+  // blocks are dealt to the 8 XCDs round robin; give XCD j the j-th
+  // contiguous run of tiles
+  const int xcd = bid & 7, local = bid >> 3;
+  const int base = n >> 3, rem = n & 7;
+  return xcd * base + min(xcd, rem) + local;
+}
+
+// Streaming kernels: one 64x4 pixel tile per block of a 1-D grid, tiles in
+// XCD bands.
+__device__ __forceinline__ void stream_xy(int W, int H, int &x, int &y) {
+  const int tx = (W + 63) >> 6, n = tx * ((H + 3) >> 2);
+  const int t = xcd_tile((int)blockIdx.x, n);
+  x = (t % tx) * 64 + (int)threadIdx.x;
+  y = (t / tx) * 4 + (int)threadIdx.y;
+}
+
 __device__ __forceinline__ V3 load3(const float *p, int plane, int idx) {
   return V3{p[idx], p[plane + idx], p[2 * plane + idx]};
 }
@@ -149,8 +169,8 @@ __device__ __forceinline__ int reproject_pixel(const ParamsK &P, const ViewK &cu
 // f_r L cos / D (null samples count zero), the Monte Carlo estimator of the
 // reflected radiance with the mixture density of the samples.
 __global__ __launch_bounds__(256) void k_estimate(ParamsK P, ViewK v, SamplesK S, float *__restrict__ out) {
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
+  int x, y;
+  stream_xy(v.W, v.H, x, y);
   if (x >= v.W || y >= v.H) return;
   const int plane = v.H * v.pitch;
   const int idx = y * v.pitch + x;
@@ -298,8 +318,8 @@ template <typename TG>
 __global__ __launch_bounds__(256) void k_reproject(ParamsK P, ViewK cur, ViewK prev,
                                                    const TG *__restrict__ gprev, TG *__restrict__ gout,
                                                    int32_t *__restrict__ src_index, int has_prev) {
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
+  int x, y;
+  stream_xy(cur.W, cur.H, x, y);
   if (x >= cur.W || y >= cur.H) return;
   float g[8];
   const int idx = y * cur.pitch + x;
@@ -311,8 +331,8 @@ __global__ __launch_bounds__(256) void k_reproject(ParamsK P, ViewK cur, ViewK p
 template <typename TG>
 __global__ __launch_bounds__(256) void k_sample(ParamsK P, ViewK v, const TG *__restrict__ gamma,
                                                 SamplesK S) {
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
+  int x, y;
+  stream_xy(v.W, v.H, x, y);
   if (x >= v.W || y >= v.H) return;
   float g[8];
   const int idx = y * v.pitch + x;
@@ -350,8 +370,8 @@ __global__ __launch_bounds__(256) void k_reproject_sample(ParamsK P, ViewK cur, 
                                                           const TG *__restrict__ gprev,
                                                           TG *__restrict__ gout, SamplesK S,
                                                           int has_prev) {
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
+  int x, y;
+  stream_xy(cur.W, cur.H, x, y);
   if (x >= cur.W || y >= cur.H) return;
   reproject_sample_pixel(P, cur, prev, gprev, gout, S, has_prev != 0, x, y);
 }
@@ -361,8 +381,8 @@ template <typename TG>
 __global__ __launch_bounds__(256) void k_pdf(ParamsK P, ViewK v, const TG *__restrict__ gamma, int n_per_px,
                                              const float *__restrict__ dir, float *__restrict__ pmix,
                                              float *__restrict__ pguide, float *__restrict__ pbrdf) {
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
+  int x, y;
+  stream_xy(v.W, v.H, x, y);
   if (x >= v.W || y >= v.H) return;
   const int plane = v.H * v.pitch;
   const int idx = y * v.pitch + x;
@@ -400,8 +420,8 @@ __global__ __launch_bounds__(256) void k_pdf(ParamsK P, ViewK v, const TG *__res
 
 __global__ __launch_bounds__(256) void k_light(LightsK Lt, ViewK v, const uint8_t *__restrict__ vis,
                                                SamplesK S) {
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
+  int x, y;
+  stream_xy(v.W, v.H, x, y);
   if (x >= v.W || y >= v.H) return;
   const int plane = v.H * v.pitch;
   const int idx = y * v.pitch + x;
@@ -424,13 +444,6 @@ __global__ __launch_bounds__(256) void k_light(LightsK Lt, ViewK v, const uint8_
 // in the last slot for records that are not BRDF-strategy samples or lie
 // outside the image (such records add nothing to any sum, which is the same
 // as leaving them out of the training set).
-__device__ __forceinline__ int xcd_tile(int bid, int n) {
-  // blocks are dealt to the 8 XCDs round robin; give XCD j the j-th
-  // contiguous run of tiles
-  const int xcd = bid & 7, local = bid >> 3;
-  const int base = n >> 3, rem = n & 7;
-  return xcd * base + min(xcd, rem) + local;
-}
 
 template <int TW, int TH>
 __device__ __forceinline__ void stage_records(const ViewK &v, const SamplesK &S, float4 *lds, int tx0,
@@ -1023,6 +1036,8 @@ __global__ __launch_bounds__(256) void k_rs_batched(const char *__restrict__ tab
   if (hd->dtype != dtype) return;
   const int n_views = hd->n_views, n_tiles = hd->rs_tiles;
   const BatchViewK *vs = batch_views(table);
+  // interleaved, not banded: the views are ordered by spp, so contiguous
+  // bands would give one XCD up to 8x the sampling work of another
   for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const BatchViewK &bv = vs[batch_find<false>(vs, n_views, t)];
     const int local = t - bv.rs_begin;

@@ -130,7 +130,8 @@ SamplesK to_k(const pg_samples *s) {
   return k;
 }
 
-dim3 stream_grid(int W, int H) { return dim3((W + 63) / 64, (H + 3) / 4); }
+// 1-D grid of 64x4 tiles (the kernels map blocks to tiles in XCD bands).
+dim3 stream_grid(int W, int H) { return dim3(((W + 63) / 64) * ((H + 3) / 4)); }
 
 template <typename F>
 pg_status dispatch_dtype(int dtype, F &&f) {
