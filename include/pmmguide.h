@@ -62,8 +62,9 @@ typedef enum pg_status {
 typedef enum pg_dtype { PG_F32 = 0, PG_F16 = 1, PG_BF16 = 2 } pg_dtype;
 
 enum {
-  PG_NO_CLAMP = 1, /* do not clamp pi after the M-step                        */
-  PG_EM_BATCH = 2  /* pg_em_update: iterate plain batch EM on a fixed set     */
+  PG_NO_CLAMP = 1,    /* do not clamp pi after the M-step                     */
+  PG_EM_BATCH = 2,    /* pg_em_update: iterate plain batch EM on a fixed set  */
+  PG_STALE_RESET = 4  /* online update: reset a stale history (stale_tau)     */
 };
 
 /* One view's G-buffer (Sec. 3.1 "rasterized G-Buffer"); all FP32 device planes. */
@@ -114,9 +115,11 @@ typedef struct pg_params {
   float rough_min;  /* guide only if roughness >= rough_min, 0.1                 */
   float s_diffuse;  /* probability of the cosine lobe in BRDF sampling, 0.5      */
   float f0;         /* Schlick reflectance at normal incidence, 0.04             */
-  uint32_t flags;   /* PG_NO_CLAMP | PG_EM_BATCH                                  */
+  uint32_t flags;   /* PG_NO_CLAMP | PG_EM_BATCH | PG_STALE_RESET                 */
   int32_t tile_w, tile_h; /* training tile; 0 = library default; results do not
                              depend on it                                         */
+  float stale_tau;  /* with PG_STALE_RESET: nats per unit weight (see
+                       pg_em_update); ignored otherwise                           */
 } pg_params;
 
 /* Analytic stand-in for the traced incident radiance (the paper traces rays,
@@ -194,8 +197,14 @@ pg_status pg_light_field(const pg_lights *lights, const pg_view *v, const uint8_
  * most kMax).  An empty batch leaves the pixel unchanged.
  * With PG_EM_BATCH in p->flags, `iterations` rounds of plain batch EM run on
  * the same training set (mu, Sigma, pi replaced; W and k kept); otherwise
- * `iterations` must be 1.  Reads samples->dir, pdf_brdf, strategy,
- * radiance. */
+ * `iterations` must be 1.  With PG_STALE_RESET (online update only), a
+ * trained model (k >= 1) is first tested against its training set: with the
+ * E-step densities, l_m = sum w log(pi p_g + (1 - pi) p_b) under the model
+ * and l_r the same under a new model (the reset lobe and pi_init); when
+ * l_m - l_r < -stale_tau sum w the model is reset before the E-step, so the
+ * batch alone trains it (a reading of the stronger rejection of reprojected
+ * models that Sec. 5 leaves open; the training set is the one drawn for the
+ * model's k).  Reads samples->dir, pdf_brdf, strategy, radiance. */
 pg_status pg_em_update(const pg_params *p, const pg_view *v, const pg_samples *in,
                        pg_gamma gamma_inout, int32_t iterations, void *stream);
 

@@ -14,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 NO_CLAMP = 1
+STALE_RESET = 4
 STRATEGY_NONE, STRATEGY_BRDF, STRATEGY_GUIDED, STRATEGY_GUIDED_NULL, STRATEGY_BRDF_NULL = range(5)
 
 
@@ -33,7 +34,7 @@ class Params(C.Structure):
         ("pi_init", C.c_float), ("pi_lo", C.c_float), ("pi_hi", C.c_float),
         ("eps_sigma", C.c_float), ("tau_depth", C.c_float), ("tau_normal", C.c_float),
         ("rough_min", C.c_float), ("s_diffuse", C.c_float), ("f0", C.c_float),
-        ("flags", C.c_uint32),
+        ("flags", C.c_uint32), ("stale_tau", C.c_float),
     ]
 
 
@@ -42,7 +43,8 @@ class Rect(C.Structure):
 
 
 DEFAULTS = dict(k_max=16, radius=3, pi_init=0.05, pi_lo=0.05, pi_hi=0.95, eps_sigma=2.5e-4,
-                tau_depth=0.1, tau_normal=0.9, rough_min=0.1, s_diffuse=0.5, f0=0.04, flags=0)
+                tau_depth=0.1, tau_normal=0.9, rough_min=0.1, s_diffuse=0.5, f0=0.04, flags=0,
+                stale_tau=0.0)
 
 _lib = None
 
@@ -82,6 +84,7 @@ def _declare(L):
     L.orc_em.argtypes = [P, P, i32, P, P, P, P, P, i32, i32, P, Rect]
     L.orc_nll.argtypes = [P, P, i32, P, P, P, P, P, P, P, P, Rect]
     L.orc_estimate.argtypes = [P, P, i32, P, P, P, P, P, Rect]
+    L.orc_stale_margin.argtypes = [P, P, i32, P, P, P, P, P, P, Rect]
     L.orc_reference.argtypes = [P, P, i32, P, C.c_double, P, i32, i64, P, P, P]
     L.orc_num_threads.restype = i32
 
@@ -297,6 +300,20 @@ def em(P, view, rec, gamma, iterations=1, batch=False, rect=None, with_stats=Fal
     lib().orc_em(C.byref(P), C.byref(view.c), spp, _ptr(d), _ptr(pb), _ptr(st), _ptr(L), _ptr(g),
                  iterations, int(bool(batch)), _ptr(stats), _rect(view, rect))
     return (g, stats) if with_stats else g
+
+
+def stale_margin(P, view, rec, gamma, rect=None):
+    """Per-pixel margin of the stale-history decision (negative = reset; NaN
+    where it does not apply)."""
+    spp = rec["strategy"].shape[0]
+    d, pb = _f64(rec["dir"]), _f64(rec["pdf_brdf"])
+    st = np.ascontiguousarray(rec["strategy"], dtype=np.uint8)
+    L = _f64(rec["radiance"])
+    g = _f64(gamma)
+    out = np.zeros((view.height, view.width))
+    lib().orc_stale_margin(C.byref(P), C.byref(view.c), spp, _ptr(d), _ptr(pb), _ptr(st), _ptr(L), _ptr(g),
+                           _ptr(out), _rect(view, rect))
+    return out
 
 
 def estimate(P, view, rec, rect=None):

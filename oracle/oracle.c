@@ -814,6 +814,77 @@ static void gather_set(const orc_params *P, const orc_view *v, int32_t spp, cons
   (void)H;
 }
 
+/* Rejection of a stale history (the paper leaves stronger rejection of
+ * reprojected models open, Sec. 5): with the E-step's densities of the
+ * batch, compare the weighted log-likelihood under the reprojected model,
+ *   l_m = sum w log(pi p_g + (1 - pi) p_b),
+ * with the one under a new model (the reset lobe, pi = pi_init),
+ *   l_r = sum w log(pi_init p_g,new + (1 - pi_init) p_b);
+ * the history is stale when l_m - l_r < -stale_tau sum w. */
+static double mixture_at(const gauss_t *G, double pi, const double u[2], double pb) {
+  return pi * gauss_pdf_sq(G, u) / (2.0 * PI) + (1.0 - pi) * pb;
+}
+
+static int stale_history(const orc_params *P, const double g[NCH], int n, double u[][2], const double *w,
+                         const double *pb) {
+  double g0[NCH];
+  gamma_reset(P, g0);
+  const gauss_t G = pixel_gauss(P, g), G0 = pixel_gauss(P, g0);
+  double lm = 0.0, lr = 0.0, ws = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const double dm = mixture_at(&G, g[5], u[j], pb[j]);
+    const double dr = mixture_at(&G0, g0[5], u[j], pb[j]);
+    if (!(w[j] > 0.0) || !(dm > 0.0) || !(dr > 0.0)) continue;
+    lm += w[j] * log(dm);
+    lr += w[j] * log(dr);
+    ws += w[j];
+  }
+  return ws > 0.0 && (lm - lr) < -(double)P->stale_tau * ws;
+}
+
+/* The margin of that decision per pixel: (l_m - l_r) / sum w + stale_tau
+ * (negative: the history is reset); NaN where the test does not apply (not
+ * guided, k < 1, or no weight).  Test infrastructure for decisions taken in
+ * different precisions. */
+void orc_stale_margin(const orc_params *P, const orc_view *v, int32_t spp, const double *dir,
+                      const double *pdf_brdf, const uint8_t *strategy, const double *radiance,
+                      const double *gamma, double *out, orc_rect r) {
+  const int64_t pl = (int64_t)v->height * v->pitch;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int y = r.y0; y < r.y1; ++y) {
+    tset_t *T = (tset_t *)malloc(sizeof(tset_t));
+    for (int x = r.x0; x < r.x1; ++x) {
+      const int64_t idx = (int64_t)y * v->pitch + x;
+      out[idx] = NAN;
+      pixel_t px = load_pixel(P, v, idx);
+      double g[NCH];
+      gamma_get(gamma, pl, idx, g);
+      if (!px.guided || (int)g[7] < 1) continue;
+      gather_set(P, v, spp, dir, pdf_brdf, strategy, radiance, x, y, (int)g[7], T);
+      gauss_t G = pixel_gauss(P, g);
+      double u[MAX_SET][2], w[MAX_SET], gam[MAX_SET], pg[MAX_SET], pb[MAX_SET];
+      int n = 0;
+      for (int j = 0; j < T->n; ++j)
+        if (estep_sample(P, &px, &G, g[5], T->dir[j], T->L[j], T->psrc[j], u[n], &w[n], &gam[n], &pg[n], &pb[n]))
+          ++n;
+      double g0[NCH];
+      gamma_reset(P, g0);
+      const gauss_t G0 = pixel_gauss(P, g0);
+      double lm = 0.0, lr = 0.0, ws = 0.0;
+      for (int j = 0; j < n; ++j) {
+        const double dm = mixture_at(&G, g[5], u[j], pb[j]);
+        const double dr = mixture_at(&G0, g0[5], u[j], pb[j]);
+        if (!(w[j] > 0.0) || !(dm > 0.0) || !(dr > 0.0)) continue;
+        lm += w[j] * log(dm);
+        lr += w[j] * log(dr);
+        ws += w[j];
+      }
+      if (ws > 0.0) out[idx] = (lm - lr) / ws + (double)P->stale_tau;
+    }
+    free(T);
+  }
+}
+
 /* Online EM update (Sec. 3.2): E-step over the training set with the
  * reprojected model, then the stepwise merge.  With batch != 0 the E- and
  * M-steps are iterated on the same training set with eta = 1 (plain batch EM:
@@ -840,12 +911,24 @@ void orc_em(const orc_params *P, const orc_view *v, int32_t spp, const double *d
       int iters = batch ? iterations : 1;
       for (int it = 0; it < iters; ++it) {
         gauss_t G = pixel_gauss(P, g);
-        double u[MAX_SET][2], w[MAX_SET], gam[MAX_SET];
+        double u[MAX_SET][2], w[MAX_SET], gam[MAX_SET], pg[MAX_SET], pb[MAX_SET];
         int n = 0;
         for (int j = 0; j < T->n; ++j) {
           if (estep_sample(P, &px, &G, g[5], T->dir[j], T->L[j], T->psrc[j], u[n], &w[n],
-                           &gam[n], NULL, NULL))
+                           &gam[n], &pg[n], &pb[n]))
             ++n;
+        }
+        if (!batch && (P->flags & ORC_STALE_RESET) && (int)g[7] >= 1 &&
+            stale_history(P, g, n, u, w, pb)) {
+          /* the history explains the batch worse than a new model: start over */
+          gamma_reset(P, g);
+          G = pixel_gauss(P, g);
+          n = 0;
+          for (int j = 0; j < T->n; ++j) {
+            if (estep_sample(P, &px, &G, g[5], T->dir[j], T->L[j], T->psrc[j], u[n], &w[n],
+                             &gam[n], NULL, NULL))
+              ++n;
+          }
         }
         double st[7];
         orc_batch_stats(n, &u[0][0], w, gam, st);

@@ -43,7 +43,7 @@ typedef struct orc_view {
   const uint8_t *disocc;  /* [H*pitch] nonzero = disoccluded; NULL = none      */
 } orc_view;
 
-enum { ORC_NO_CLAMP = 1 };
+enum { ORC_NO_CLAMP = 1, ORC_STALE_RESET = 4 };
 
 typedef struct orc_params {
   uint64_t seed;
@@ -58,7 +58,10 @@ typedef struct orc_params {
   float rough_min;      /* minimum roughness for guiding                       */
   float s_diffuse;      /* probability of the diffuse lobe in BRDF sampling   */
   float f0;             /* Schlick reflectance at normal incidence             */
-  uint32_t flags;       /* ORC_NO_CLAMP                                         */
+  uint32_t flags;       /* ORC_NO_CLAMP, ORC_STALE_RESET                        */
+  float stale_tau;      /* with ORC_STALE_RESET: reset a trained model whose
+                           weighted log-likelihood of the batch is below a new
+                           model's by more than stale_tau per unit weight     */
 } orc_params;
 
 typedef struct orc_rect { int32_t x0, y0, x1, y1; } orc_rect;
@@ -115,6 +118,11 @@ void orc_nll(const orc_params *P, const orc_view *v, int32_t spp, const double *
              const double *pdf_brdf, const uint8_t *strategy, const double *radiance,
              const double *theta, const double *grad_out, double *grad, double *nll,
              orc_rect r);
+/* Margin of the stale-history decision per pixel, (l_m - l_r)/sum w +
+ * stale_tau (negative = reset), NaN where it does not apply. */
+void orc_stale_margin(const orc_params *P, const orc_view *v, int32_t spp, const double *dir,
+                      const double *pdf_brdf, const uint8_t *strategy, const double *radiance,
+                      const double *gamma, double *out, orc_rect r);
 /* First-bounce estimate per pixel: mean over samples of f_r L cos / D
  * (null samples contribute zero). */
 void orc_estimate(const orc_params *P, const orc_view *v, int32_t spp, const double *dir,

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libpmmguide.so")
 
 PG_OK, PG_ERR_ARG, PG_ERR_UNSUPPORTED, PG_ERR_HIP = 0, 1, 2, 3
 PG_F32, PG_F16, PG_BF16 = 0, 1, 2
-PG_NO_CLAMP, PG_EM_BATCH = 1, 2
+PG_NO_CLAMP, PG_EM_BATCH, PG_STALE_RESET = 1, 2, 4
 MAX_LIGHTS = 8
 
 STRATEGY_NONE, STRATEGY_BRDF, STRATEGY_GUIDED, STRATEGY_GUIDED_NULL, STRATEGY_BRDF_NULL = range(5)
@@ -49,6 +49,7 @@ class PgParams(C.Structure):
         ("eps_sigma", C.c_float), ("tau_depth", C.c_float), ("tau_normal", C.c_float),
         ("rough_min", C.c_float), ("s_diffuse", C.c_float), ("f0", C.c_float),
         ("flags", C.c_uint32), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
+        ("stale_tau", C.c_float),
     ]
 
 

@@ -23,6 +23,7 @@ struct ParamsK {
   int k_max;
   float pi_init, pi_lo, pi_hi, eps, tau_z, tau_n, rough_min, s_d, f0;
   uint32_t flags;
+  float stale_tau;
 };
 
 struct SamplesK {
@@ -32,6 +33,7 @@ struct SamplesK {
 };
 
 constexpr uint32_t kNoClamp = 1u;
+constexpr uint32_t kStaleReset = 4u;
 constexpr int kR = 3;                       // pick radius: 7x7 window
 constexpr int kSide = 2 * kR + 1;
 constexpr int kCand = kSide * kSide - 1;    // 48 neighbours
@@ -614,6 +616,36 @@ __device__ __forceinline__ int build_list(const ParamsK &P, const float4 *lds, u
   return n;
 }
 
+// Rejection of a stale history (the stronger rejection of reprojected models
+// that Sec. 5 leaves open, as read here): the weighted log-likelihood of the
+// pixel's training set under the model, l_m = sum w log(pi p_g + (1 - pi)
+// p_b), against the one under a new model (reset lobe, pi_init), l_r; the
+// history is stale when l_m - l_r < -stale_tau sum w.  A pass of its own
+// over the list, so that the E-step is untouched when the test is off.
+__device__ __forceinline__ bool stale_history(const ParamsK &P, const Pixel &px, const float g[8],
+                                              const float4 *lds, const uint16_t *list, int me, int len, int nt) {
+  const Gauss G = gauss_setup(g[0], g[1], g[2], g[3], g[4], P.eps);
+  const Gauss G0 = gauss_setup(0.5f, 0.5f, 1.0f / 12.0f, 0.0f, 1.0f / 12.0f, P.eps);
+  const float pi = g[5], pi0 = P.pi_init;
+  float lm = 0.0f, lr = 0.0f, ws = 0.0f;
+  for (int j = 0; j < len; ++j) {
+    const float4 r = lds[list[j * nt + me]];
+    const V3 l = to_local(px.f, V3{r.x, r.y, r.z});
+    if (l.z <= 0.0f) continue;
+    float ux, uy, f, pb;
+    hemi2sq(l, ux, uy);
+    brdf_eval(px, l, f, pb);
+    const float w = r.w * f * l.z;
+    const float dm = fmaf(pi, gauss_pdf_acc(G, ux, uy), (1.0f - pi) * pb);
+    const float dr = fmaf(pi0, gauss_pdf_acc(G0, ux, uy), (1.0f - pi0) * pb);
+    if (!(w > 0.0f) || !(dm > 0.0f) || !(dr > 0.0f)) continue;
+    lm = fmaf(w, __logf(dm), lm);
+    lr = fmaf(w, __logf(dr), lr);
+    ws += w;
+  }
+  return ws > 0.0f && (lm - lr) < -P.stale_tau * ws;
+}
+
 // Counting sort of the tile's items by decreasing work `len` (0 .. kMaxLen -
 // 1) so that the lanes of a wave carry nearly equal work (the order inside a
 // class is irrelevant: a pixel's arithmetic does not depend on the lane that
@@ -723,7 +755,7 @@ __device__ __forceinline__ void em_load(const ViewK &v, const SamplesK &S, const
 // them (the write-back area overlaps the records).
 // Dynamic LDS: records [spp][SH][SW] float4, then lists [spp + 20][NT]
 // uint16; the write-back reuses the area ([8][NT] float).
-template <typename TG, int TW, int TH>
+template <typename TG, int TW, int TH, bool STALE = false>
 __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const SamplesK &S, TG *gamma,
                                         int iterations, int batch, int tx0, int ty0, int rot, float4 *lds,
                                         EmShared<TW * TH> &sh, const EmInput<TW, TH> &R) {
@@ -775,6 +807,7 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
     const int idx = (ty0 + me / TW) * v.pitch + tx0 + me % TW;
     gamma_load(gamma, plane, idx, g);
     c.px = make_pixel(P, load3(v.n, plane, idx), load3(v.o, plane, idx), v.rough[idx], v.alb[idx]);
+    if (STALE && !batch && g[7] >= 1.0f && stale_history(P, c.px, g, lds, list, me, len, NT)) gamma_reset(P, g);
   }
   if (len > 0) {  // otherwise no training sample (or no pixel): the model stays as it is
     const int iters = batch ? iterations : 1;
@@ -855,7 +888,7 @@ struct TileBand {
 // LDS and registers of a tile, several blocks share each CU, which hides the
 // loads of one block behind the arithmetic of the others better than a
 // persistent loop with register prefetch.
-template <typename TG, int TW, int TH>
+template <typename TG, int TW, int TH, bool STALE>
 __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(8))) void k_em(ParamsK P, ViewK v, SamplesK S, TG *__restrict__ gamma,
                                                int iterations, int batch, int tiles_x, int n_tiles) {
   extern __shared__ float4 lds[];  // records, state and lists (see em_tile)
@@ -864,7 +897,7 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(8))) voi
   const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
   EmInput<TW, TH> R;
   em_load(v, S, gamma, tx0, ty0, R);
-  em_tile<TG, TW, TH>(P, v, S, gamma, iterations, batch, tx0, ty0, (int)blockIdx.x, lds, sh, R);
+  em_tile<TG, TW, TH, STALE>(P, v, S, gamma, iterations, batch, tx0, ty0, (int)blockIdx.x, lds, sh, R);
 }
 
 // ---------------------------------------------------------------------------

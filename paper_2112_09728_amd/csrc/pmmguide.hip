@@ -51,6 +51,7 @@ pg_status check_params(const pg_params *p) {
   if (!(p->eps_sigma > 0.0f) && p->eps_sigma != 0.0f) return fail(PG_ERR_ARG, "eps_sigma must be >= 0");
   if (!(p->pi_lo <= p->pi_hi)) return fail(PG_ERR_ARG, "pi_lo > pi_hi");
   if (!(p->s_diffuse >= 0.0f && p->s_diffuse <= 1.0f)) return fail(PG_ERR_ARG, "s_diffuse outside [0, 1]");
+  if ((p->flags & PG_STALE_RESET) && p->stale_tau != p->stale_tau) return fail(PG_ERR_ARG, "stale_tau is NaN");
   return PG_OK;
 }
 
@@ -101,6 +102,7 @@ ParamsK to_k(const pg_params *p) {
   k.s_d = p->s_diffuse;
   k.f0 = p->f0;
   k.flags = p->flags;
+  k.stale_tau = p->stale_tau;
   return k;
 }
 
@@ -202,7 +204,10 @@ pg_status launch_em_t(const ParamsK &P, const ViewK &v, const SamplesK &S, TG *g
   const int tx = (v.W + TW - 1) / TW, ty = (v.H + TH - 1) / TH;
   const int n = tx * ty;
   const size_t lds = tile_lds(Tile{TW, TH}, S.spp);
-  hipLaunchKernelGGL((k_em<TG, TW, TH>), dim3(n), dim3(TW * TH), lds, st, P, v, S, g, iters, batch, tx, n);
+  if ((P.flags & kStaleReset) && !batch)
+    hipLaunchKernelGGL((k_em<TG, TW, TH, true>), dim3(n), dim3(TW * TH), lds, st, P, v, S, g, iters, batch, tx, n);
+  else
+    hipLaunchKernelGGL((k_em<TG, TW, TH, false>), dim3(n), dim3(TW * TH), lds, st, P, v, S, g, iters, batch, tx, n);
   return PG_OK;
 }
 
@@ -282,6 +287,7 @@ pg_status check_batch_view(const pg_batch_view &b, int dtype) {
       (st = check_lights(&b.lights, b.vis)))
     return st;
   if (b.params.flags & PG_EM_BATCH) return fail(PG_ERR_UNSUPPORTED, "the batched frame runs the online update only");
+  if (b.params.flags & PG_STALE_RESET) return fail(PG_ERR_UNSUPPORTED, "the batched frame has no stale-history reset");
   if (b.gamma_out.dtype != dtype) return fail(PG_ERR_ARG, "views store Gamma in different dtypes");
   if (b.params.frame > 0) {
     if ((st = check_view(&b.prev, "prev", false)) || (st = check_gamma(b.gamma_in, "gamma_in"))) return st;

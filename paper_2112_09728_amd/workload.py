@@ -153,9 +153,10 @@ class Sequence:
     ``disocc`` [H][W]; frames must be requested in order 0, 1, 2, ..."""
 
     def __init__(self, width: int, height: int, seed: int, moving: bool = True,
-                 disocc_rate: float = 0.02, margin: int = 64):
+                 disocc_rate: float = 0.02, margin: int = 64, light_moves_at: int | None = None):
         self.width, self.height, self.seed = width, height, seed
         self.moving, self.disocc_rate, self.margin = moving, disocc_rate, margin
+        self.light_moves_at = light_moves_at
         self.world = make_scene(width, height, seed, margin=margin if moving else 0)
         self.offset = np.zeros(2)
         self.t = -1
@@ -192,6 +193,20 @@ class Sequence:
         # content moves opposite to the window: motion = -(window step)
         out["motion"] = np.broadcast_to((-step).astype(np.float32)[:, None, None], (2, H, W)).copy()
         out["disocc"] = mask
+        if self.light_moves_at is not None and t >= self.light_moves_at:
+            # the most powerful light (power of an SG lobe ~ c / lambda) jumps
+            # to a new direction on the upper hemisphere (a dynamic light:
+            # trained lobes become stale)
+            lights = np.array(out["lights"], np.float32, copy=True)
+            k = int(np.argmax(lights[:, 4] / lights[:, 3]))
+            rng = _rng(self.seed, _S_MOTION, 10_000)
+            z = rng.uniform(0.3, 0.95)
+            phi = rng.uniform(0.0, 2.0 * np.pi)
+            new = np.array([np.sqrt(1 - z * z) * np.cos(phi), np.sqrt(1 - z * z) * np.sin(phi), z])
+            if np.dot(new, lights[k, :3]) > 0.5:  # make it a real jump
+                new[:2] = -new[:2]
+            lights[k, :3] = new.astype(np.float32)
+            out["lights"] = lights
         return out
 
 

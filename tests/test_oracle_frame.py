@@ -483,3 +483,76 @@ def test_estimate_is_unbiased_against_quadrature(rough):
               for s in range(0, spp, 64)]
     se = np.std(single) / np.sqrt(spp)
     assert abs(e - truth) < 5 * se, (e, truth, se)
+
+
+# ------------------------------------------------------ stale-history reset (f3)
+def _stale_setup():
+    sc, v, rec, g0 = _em_setup(W=32, H=24, spp=2, seed=43)
+    rng = np.random.default_rng(43)
+    H, W = g0.shape[1:]
+    g = g0.copy()
+    # trained histories: lobes at random places, some far from where the
+    # radiance comes from
+    g[0] = rng.uniform(0.1, 0.9, (H, W))
+    g[1] = rng.uniform(0.1, 0.9, (H, W))
+    g[2] = g[4] = 0.002
+    g[3] = 0.0
+    g[5] = rng.uniform(0.3, 0.9, (H, W))
+    g[6] = rng.uniform(1.0, 5.0, (H, W))
+    g[7] = 8
+    return sc, v, rec, g
+
+
+def test_stale_reset_limits():
+    """tau = +inf never resets (the plain update); tau = -inf resets every
+    trained model that has a batch, which then equals the update of a new
+    model on the same training set."""
+    sc, v, rec, g = _stale_setup()
+    P = O.params(43, frame=3)
+    plain = O.em(P, v, rec, g)
+    never = O.em(O.params(43, frame=3, flags=O.STALE_RESET, stale_tau=1e30), v, rec, g)
+    assert np.array_equal(never, plain)
+    always = O.em(O.params(43, frame=3, flags=O.STALE_RESET, stale_tau=-1e30), v, rec, g)
+    # a new model with no evidence (W = 0) but the same k draws the same
+    # training set, and its merge gives the batch estimate: the same mu,
+    # Sigma and pi as the reset (pi up to rounding: B1/B0 against
+    # (B1/9)/(B0/9))
+    fresh = g.copy()
+    fresh[:7] = np.array([0.5, 0.5, 1 / 12, 0.0, 1 / 12, float(np.float32(0.05)), 0.0])[:, None, None]
+    new = O.em(P, v, rec, fresh)
+    trained = always[7] != g[7]  # pixels that had a batch
+    assert trained.mean() > 0.5
+    assert np.array_equal(always[:5, trained], new[:5, trained])
+    assert np.abs(always[5, trained] - new[5, trained]).max() < 1e-15
+    assert (always[7][trained] == 1).all()
+
+
+def test_stale_reset_keeps_a_history_equal_to_a_new_model():
+    """A trained model whose lobe and pi are those of a new model explains the
+    batch exactly as well as a new model (l_m = l_r): it is kept for tau = 0
+    and reset for any tau < 0."""
+    sc, v, rec, g = _stale_setup()
+    g[:6] = np.array([0.5, 0.5, 1 / 12, 0.0, 1 / 12, float(np.float32(0.05))])[:, None, None]
+    plain = O.em(O.params(43, frame=3), v, rec, g)
+    keep = O.em(O.params(43, frame=3, flags=O.STALE_RESET, stale_tau=0.0), v, rec, g)
+    assert np.array_equal(keep, plain)
+    reset = O.em(O.params(43, frame=3, flags=O.STALE_RESET, stale_tau=-1e-9), v, rec, g)
+    trained = plain[7] != g[7]
+    assert (reset[7][trained] == 1).all() and (plain[7][trained] == 9).all()
+
+
+def test_stale_reset_picks_the_lobes_without_evidence():
+    """With a finite tau only some histories are reset, and those are the
+    lobes that explain little of the batch: their Gaussian's share B1/B0 of
+    the batch evidence (under the history) is lower than the kept lobes'.
+    Such a lobe barely moves in the plain update, since its posterior weight
+    is small; that persistence is what the reset removes."""
+    sc, v, rec, g = _stale_setup()
+    P = O.params(43, frame=3)
+    plain, stats = O.em(P, v, rec, g, with_stats=True)
+    out = O.em(O.params(43, frame=3, flags=O.STALE_RESET, stale_tau=0.5), v, rec, g)
+    trained = plain[7] != g[7]
+    reset = trained & (out[7] == 1)
+    assert 0 < reset.sum() < trained.sum()
+    share = stats[1] / np.where(stats[0] > 0, stats[0], 1)
+    assert np.median(share[reset]) < 0.5 * np.median(share[trained & ~reset])
