@@ -86,6 +86,10 @@ def _declare(L):
     L.orc_estimate.argtypes = [P, P, i32, P, P, P, P, P, Rect]
     L.orc_stale_margin.argtypes = [P, P, i32, P, P, P, P, P, P, Rect]
     L.orc_reference.argtypes = [P, P, i32, P, C.c_double, P, i32, i64, P, P, P]
+    L.orc_reproject_k.argtypes = [P, i32, P, P, P, P, P, Rect]
+    L.orc_sample_k.argtypes = [P, i32, P, P, i32, P, P, P, P, P, Rect]
+    L.orc_pdf_k.argtypes = [P, i32, P, P, i32, P, P, Rect]
+    L.orc_em_k.argtypes = [P, i32, P, i32, P, P, P, P, P, Rect]
     L.orc_num_threads.restype = i32
 
 
@@ -356,6 +360,55 @@ def nll(P, view, rec, theta, grad_out=None, rect=None):
     return out, grad
 
 
+# --- K Gaussian lobes per pixel: state [6K + 2][H][W] ------------------------
+
+def reproject_k(P, K, cur, prev, gamma_prev, rect=None, out=None):
+    H, W = cur.height, cur.width
+    g_out = np.zeros((6 * K + 2, H, W)) if out is None else out
+    src = np.full((H, W), -2, np.int32)
+    gp = None if gamma_prev is None else _f64(gamma_prev)
+    lib().orc_reproject_k(C.byref(P), K, C.byref(cur.c), None if prev is None else C.byref(prev.c),
+                          _ptr(gp), _ptr(g_out), _ptr(src), _rect(cur, rect))
+    return g_out, src
+
+
+def sample_k(P, K, view, gamma, spp, rect=None):
+    H, W = view.height, view.width
+    gamma = _f64(gamma)
+    assert gamma.shape[0] == 6 * K + 2
+    dir_ = np.zeros((3, spp, H, W))
+    pmix = np.zeros((spp, H, W))
+    pb = np.zeros((spp, H, W))
+    strat = np.zeros((spp, H, W), np.uint8)
+    margin = np.full((spp, H, W), np.inf)
+    lib().orc_sample_k(C.byref(P), K, C.byref(view.c), _ptr(gamma), spp, _ptr(dir_), _ptr(pmix),
+                       _ptr(pb), _ptr(strat), _ptr(margin), _rect(view, rect))
+    return dict(dir=dir_, pdf_mix=pmix, pdf_brdf=pb, strategy=strat, margin=margin)
+
+
+def pdf_k(P, K, view, gamma, dirs, rect=None):
+    H, W = view.height, view.width
+    dirs = _f64(dirs)
+    gamma = _f64(gamma)
+    assert gamma.shape[0] == 6 * K + 2
+    n = dirs.shape[1]
+    pmix = np.zeros((n, H, W))
+    lib().orc_pdf_k(C.byref(P), K, C.byref(view.c), _ptr(gamma), n, _ptr(dirs), _ptr(pmix), _rect(view, rect))
+    return pmix
+
+
+def em_k(P, K, view, rec, gamma, rect=None):
+    g = _f64(gamma).copy()
+    assert g.shape[0] == 6 * K + 2
+    spp = rec["strategy"].shape[0]
+    d, pb = _f64(rec["dir"]), _f64(rec["pdf_brdf"])
+    st = np.ascontiguousarray(rec["strategy"], dtype=np.uint8)
+    L = _f64(rec["radiance"])
+    lib().orc_em_k(C.byref(P), K, C.byref(view.c), spp, _ptr(d), _ptr(pb), _ptr(st), _ptr(L), _ptr(g),
+                   _rect(view, rect))
+    return g
+
+
 def num_threads():
     return lib().orc_num_threads()
 
@@ -366,9 +419,10 @@ class Frames:
     ``step(t, fr)`` takes frame t's scene dict (G-buffer, lights, vis, motion,
     disocc) and returns the per-frame intermediates."""
 
-    def __init__(self, seed, spp, view=0, **kw):
+    def __init__(self, seed, spp, view=0, lobes=1, **kw):
         self.seed = seed
         self.spp = spp
+        self.lobes = lobes
         self.view_id = view
         self.kw = kw
         self.view_prev = None
@@ -380,11 +434,16 @@ class Frames:
         P = params(self.seed, frame=t, view=self.view_id, **self.kw)
         gp = self.gamma if gamma_prev is None else gamma_prev
         prev = self.view_prev if self.view_prev is not None else v
-        g1, src = reproject(P, v, prev, gp, rect=rect)
-        rec = sample(P, v, g1, self.spp, rect=rect)
+        K = self.lobes
+        if K == 1:
+            g1, src = reproject(P, v, prev, gp, rect=rect)
+            rec = sample(P, v, g1, self.spp, rect=rect)
+        else:
+            g1, src = reproject_k(P, K, v, prev, gp, rect=rect)
+            rec = sample_k(P, K, v, g1, self.spp, rect=rect)
         rec["radiance"] = light(fr["lights"], float(fr["ambient"]), fr["vis"], rec["dir"],
                                 rec["strategy"], rect=rect)
-        g2 = em(P, v, rec, g1, rect=rect)
+        g2 = em(P, v, rec, g1, rect=rect) if K == 1 else em_k(P, K, v, rec, g1, rect=rect)
         self.gamma = g2
         self.view_prev = v
         self.last = dict(gamma_reproj=g1, src=src, rec=rec, gamma=g2)

@@ -1135,6 +1135,321 @@ void orc_reference(const orc_params *P, const orc_view *v, int32_t n_lights, con
   }
 }
 
+/* ------------------------------------------------------------------------- */
+/* K Gaussian lobes per pixel (the single lobe of Eq. (2) generalised; the
+ * paper names one 2-D Gaussian as the limit of its model, Sec. 4.1):
+ *   D(w) = sum_j pi_j N_j(M^-1 w) / (2 pi) + (1 - sum_j pi_j) p_b(w).
+ * State planes [6K + 2]: lobe j at 6j: (mu_x, mu_y, S_xx, S_xy, S_yy, pi_j),
+ * then W and k.  Readings of this extension: a new model's lobes share
+ * Sigma = I/12 and pi_init/K but start at distinct means
+ * mu_j = (0.5 + 0.2 (j - (K-1)/2), 0.5) (identical lobes would stay
+ * identical under EM); zeta picks lobe j when it falls in [c_j, c_j + pi_j)
+ * with c_j the sum of the earlier pi, else the BRDF; each lobe is merged with
+ * its own evidence B1_j like the single lobe; the clamp raises each weight to
+ * at least pi_lo / (4K) (a lobe at zero weight would never gain evidence
+ * again) and then scales them so their sum lies in [pi_lo, pi_hi]. */
+#define MAXK 4
+
+static int nch_k(int K) { return 6 * K + 2; }
+
+static void reset_k(const orc_params *P, int K, double *g) {
+  for (int j = 0; j < K; ++j) {
+    double *l = g + 6 * j;
+    l[0] = 0.5 + 0.2 * (j - 0.5 * (K - 1));
+    l[1] = 0.5;
+    l[2] = 1.0 / 12.0; l[3] = 0.0; l[4] = 1.0 / 12.0;
+    l[5] = (double)P->pi_init / K;
+  }
+  g[6 * K] = 0.0;
+  g[6 * K + 1] = 0.0;
+}
+
+static double total_pi_k(const double *g, int K) {
+  double t = 0.0;
+  for (int j = 0; j < K; ++j) t += g[6 * j + 5];
+  return t;
+}
+
+/* lobe weights used for sampling and D: zero while k = 0 or unguided */
+static int guided_k(const pixel_t *px, const double *g, int K) { return px->guided && g[6 * K + 1] >= 1.0; }
+
+static double mixture_k(const orc_params *P, const pixel_t *px, const double *g, int K, const double l[3],
+                        double *pb_out) {
+  double pb = 0.0, D = 0.0;
+  if (px->valid && l[2] > 0.0) {
+    pb = brdf_pdf(px->wo, l, px->alpha, (double)P->s_diffuse);
+    double u[2];
+    hemi2sq(l, u);
+    double tot = 0.0;
+    if (guided_k(px, g, K)) {
+      for (int j = 0; j < K; ++j) {
+        gauss_t G = gauss_setup(g + 6 * j, (double)P->eps_sigma);
+        D += g[6 * j + 5] * (gauss_pdf_sq(&G, u) / (2.0 * PI));
+        tot += g[6 * j + 5];
+      }
+    }
+    D += (1.0 - tot) * pb;
+  }
+  if (pb_out) *pb_out = pb;
+  return D;
+}
+
+void orc_reproject_k(const orc_params *P, int32_t K, const orc_view *cur, const orc_view *prev,
+                     const double *gamma_prev, double *gamma_out, int32_t *src_index, orc_rect r) {
+  const int NC = nch_k(K);
+  const int64_t pl = (int64_t)cur->height * cur->pitch;
+  const int64_t ppl = prev ? (int64_t)prev->height * prev->pitch : 0;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int y = r.y0; y < r.y1; ++y) {
+    for (int x = r.x0; x < r.x1; ++x) {
+      const int64_t idx = (int64_t)y * cur->pitch + x;
+      double g[6 * MAXK + 2];
+      int32_t src = -1;
+      pixel_t px = load_pixel(P, cur, idx);
+      int keep = (P->frame > 0) && gamma_prev != NULL && prev != NULL && px.guided;
+      if (keep && cur->disocc && cur->disocc[idx]) keep = 0;
+      int qx = 0, qy = 0;
+      if (keep) {
+        float mx = cur->motion ? cur->motion[idx] : 0.0f;
+        float my = cur->motion ? cur->motion[pl + idx] : 0.0f;
+        float fx = ((float)x + 0.5f) - mx, fy = ((float)y + 0.5f) - my;
+        if (fx >= 0.0f && fy >= 0.0f && fx < (float)prev->width && fy < (float)prev->height) {
+          qx = (int)floorf(fx);
+          qy = (int)floorf(fy);
+        } else {
+          keep = 0;
+        }
+      }
+      int64_t qidx = 0;
+      if (keep) {
+        qidx = (int64_t)qy * prev->pitch + qx;
+        float zp = cur->depth[idx], zq = prev->depth[qidx];
+        if (fabsf(zp - zq) > P->tau_depth * zp) keep = 0;
+        const float *n = cur->normal, *m = prev->normal;
+        float nd = dot3f(n[idx], n[pl + idx], n[2 * pl + idx], m[qidx], m[ppl + qidx], m[2 * ppl + qidx]);
+        if (nd < P->tau_normal) keep = 0;
+      }
+      if (keep) {
+        for (int c = 0; c < NC; ++c) {
+          g[c] = gamma_prev[c * ppl + qidx];
+          if (!isfinite(g[c])) keep = 0;
+        }
+      }
+      if (keep) {
+        int same = 1;
+        for (int c = 0; c < 3; ++c)
+          if (cur->normal[c * pl + idx] != prev->normal[c * ppl + qidx]) same = 0;
+        if (!same) {
+          frame_t fq = make_frame(prev->normal, ppl, qidx);
+          for (int j = 0; j < K && keep; ++j) {
+            double *l = g + 6 * j;
+            double mu[2] = {fmin(fmax(l[0], 0.0), 1.0), fmin(fmax(l[1], 0.0), 1.0)};
+            double lq[3], w[3], lp[3];
+            sq2hemi(mu, lq);
+            to_world(&fq, lq, w);
+            to_local(&px.f, w, lp);
+            if (lp[2] <= 0.0) {
+              keep = 0;
+            } else {
+              double u[2];
+              hemi2sq(lp, u);
+              l[0] = u[0];
+              l[1] = u[1];
+            }
+          }
+        }
+      }
+      if (keep)
+        src = (int32_t)(qy * prev->width + qx);
+      else
+        reset_k(P, K, g);
+      for (int c = 0; c < NC; ++c) gamma_out[c * pl + idx] = g[c];
+      if (src_index) src_index[idx] = src;
+    }
+  }
+}
+
+void orc_sample_k(const orc_params *P, int32_t K, const orc_view *v, const double *gamma, int32_t spp,
+                  double *dir, double *pdf_mix, double *pdf_brdf, uint8_t *strategy, double *margin,
+                  orc_rect r) {
+  const int NC = nch_k(K);
+  const int W = v->width;
+  const int64_t pl = (int64_t)v->height * v->pitch;
+  const int64_t spl = (int64_t)spp * pl;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int y = r.y0; y < r.y1; ++y) {
+    for (int x = r.x0; x < r.x1; ++x) {
+      const int64_t idx = (int64_t)y * v->pitch + x;
+      pixel_t px = load_pixel(P, v, idx);
+      double g[6 * MAXK + 2];
+      for (int c = 0; c < NC; ++c) g[c] = gamma[c * pl + idx];
+      const int gd = guided_k(&px, g, K);
+      for (int s = 0; s < spp; ++s) {
+        const int64_t o = (int64_t)s * pl + idx;
+        uint8_t code = 0;
+        double l[3] = {0, 0, 0}, mg = INFINITY;
+        if (px.valid) {
+          uint32_t w4[4];
+          rng_words(P, (uint32_t)(y * W + x), 0, (uint32_t)s, w4);
+          double zeta = uniform24(w4[0]), xl = uniform24(w4[1]);
+          double x1 = uniform24(w4[2]), x2 = uniform24(w4[3]);
+          int lobe = -1;
+          double c = 0.0;
+          if (gd) {
+            for (int j = 0; j < K; ++j) {
+              if (lobe < 0 && zeta >= c && zeta < c + g[6 * j + 5]) lobe = j;
+              c += g[6 * j + 5];
+              mg = fmin(mg, fabs(zeta - c));
+            }
+          }
+          if (lobe >= 0) {
+            gauss_t G = gauss_setup(g + 6 * lobe, (double)P->eps_sigma);
+            double u[2];
+            gauss_sample(&G, x1, x2, u);
+            double dist = fmin(fmin(fabs(u[0]), fabs(1.0 - u[0])), fmin(fabs(u[1]), fabs(1.0 - u[1])));
+            mg = fmin(mg, dist);
+            if (u[0] >= 0.0 && u[0] <= 1.0 && u[1] >= 0.0 && u[1] <= 1.0) {
+              sq2hemi(u, l);
+              code = 2;
+            } else {
+              code = 3;
+            }
+          } else {
+            double m2 = INFINITY;
+            int ok = brdf_sample(px.wo, px.alpha, (double)P->s_diffuse, xl, x1, x2, l, &m2);
+            mg = fmin(mg, m2);
+            code = ok ? 1 : 4;
+          }
+        }
+        double w[3] = {0, 0, 0}, D = 0.0, pb = 0.0;
+        if (code == 1 || code == 2) {
+          to_world(&px.f, l, w);
+          D = mixture_k(P, &px, g, K, l, &pb);
+        }
+        for (int c = 0; c < 3; ++c) dir[c * spl + o] = w[c];
+        pdf_mix[o] = D;
+        pdf_brdf[o] = pb;
+        strategy[o] = code;
+        if (margin) margin[o] = mg;
+      }
+    }
+  }
+}
+
+void orc_pdf_k(const orc_params *P, int32_t K, const orc_view *v, const double *gamma, int32_t n_per_px,
+               const double *dirs, double *pdf_mix, orc_rect r) {
+  const int NC = nch_k(K);
+  const int64_t pl = (int64_t)v->height * v->pitch;
+  const int64_t npl = (int64_t)n_per_px * pl;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int y = r.y0; y < r.y1; ++y) {
+    for (int x = r.x0; x < r.x1; ++x) {
+      const int64_t idx = (int64_t)y * v->pitch + x;
+      pixel_t px = load_pixel(P, v, idx);
+      double g[6 * MAXK + 2];
+      for (int c = 0; c < NC; ++c) g[c] = gamma[c * pl + idx];
+      for (int s = 0; s < n_per_px; ++s) {
+        const int64_t o = (int64_t)s * pl + idx;
+        double w[3] = {dirs[o], dirs[npl + o], dirs[2 * npl + o]}, l[3];
+        double D = 0.0;
+        if (px.valid && dot3(w, w) > 0.0) {
+          normalize3(w);
+          to_local(&px.f, w, l);
+          D = mixture_k(P, &px, g, K, l, NULL);
+        }
+        pdf_mix[o] = D;
+      }
+    }
+  }
+}
+
+/* Online EM with K lobes: E-step responsibilities gam_j = pi_j p_gj / D
+ * under the model's weights, per-lobe batch statistics (B1_j, mean, scatter
+ * under the weights w gam_j), and the stepwise merge of each lobe with its
+ * evidence; then the weight clamp of the extension's reading. */
+void orc_em_k(const orc_params *P, int32_t K, const orc_view *v, int32_t spp, const double *dir,
+              const double *pdf_brdf, const uint8_t *strategy, const double *radiance, double *gamma,
+              orc_rect r) {
+  const int NC = nch_k(K);
+  const int64_t pl = (int64_t)v->height * v->pitch;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int y = r.y0; y < r.y1; ++y) {
+    tset_t *T = (tset_t *)malloc(sizeof(tset_t));
+    for (int x = r.x0; x < r.x1; ++x) {
+      const int64_t idx = (int64_t)y * v->pitch + x;
+      pixel_t px = load_pixel(P, v, idx);
+      if (!px.guided) continue;
+      double g[6 * MAXK + 2];
+      for (int c = 0; c < NC; ++c) g[c] = gamma[c * pl + idx];
+      const double kk = g[6 * K + 1], Wv = g[6 * K];
+      gather_set(P, v, spp, dir, pdf_brdf, strategy, radiance, x, y, (int)kk, T);
+      gauss_t G[MAXK];
+      for (int j = 0; j < K; ++j) G[j] = gauss_setup(g + 6 * j, (double)P->eps_sigma);
+      const double tot = total_pi_k(g, K);
+      double u[MAX_SET][2], w[MAX_SET], gam[MAX_SET][MAXK];
+      int n = 0;
+      for (int j = 0; j < T->n; ++j) {
+        double wn[3] = {T->dir[j][0], T->dir[j][1], T->dir[j][2]}, l[3];
+        if (!(dot3(wn, wn) > 0.0) || !(T->psrc[j] > 0.0)) continue;
+        normalize3(wn);
+        to_local(&px.f, wn, l);
+        if (l[2] <= 0.0) continue;
+        hemi2sq(l, u[n]);
+        w[n] = T->L[j] * brdf_f(px.wo, l, px.alpha, px.albedo, (double)P->f0) * l[2] / T->psrc[j];
+        const double pb = brdf_pdf(px.wo, l, px.alpha, (double)P->s_diffuse);
+        double a[MAXK], D = (1.0 - tot) * pb;
+        for (int q = 0; q < K; ++q) {
+          a[q] = g[6 * q + 5] * (gauss_pdf_sq(&G[q], u[n]) / (2.0 * PI));
+          D += a[q];
+        }
+        for (int q = 0; q < K; ++q) gam[n][q] = D > 0.0 ? a[q] / D : 0.0;
+        ++n;
+      }
+      double B0 = 0.0;
+      for (int j = 0; j < n; ++j) B0 += w[j];
+      if (!(B0 > 0.0)) continue;
+      const double eta = 1.0 / (kk + 1.0);
+      const double sw = (1.0 - eta) * Wv + eta * B0;
+      double pis[MAXK], ptot = 0.0;
+      for (int q = 0; q < K; ++q) {
+        double gq[MAX_SET], st[7];
+        for (int j = 0; j < n; ++j) gq[j] = gam[j][q];
+        orc_batch_stats(n, &u[0][0], w, gq, st);
+        double *l = g + 6 * q;
+        const double so = (1.0 - eta) * l[5] * Wv, sn = eta * st[1], sg = so + sn;
+        if (sg > 0.0 && st[1] > 0.0) {
+          const double al = so / sg, be = sn / sg;
+          const double dx = l[0] - st[2], dy = l[1] - st[3];
+          const double mux = al * l[0] + be * st[2], muy = al * l[1] + be * st[3];
+          const double sxx = al * l[2] + be * st[4] + al * be * dx * dx;
+          const double sxy = al * l[3] + be * st[5] + al * be * dx * dy;
+          const double syy = al * l[4] + be * st[6] + al * be * dy * dy;
+          l[0] = mux; l[1] = muy; l[2] = sxx; l[3] = sxy; l[4] = syy;
+        }
+        pis[q] = sg / sw;
+        ptot += pis[q];
+      }
+      if (!(P->flags & ORC_NO_CLAMP)) {
+        /* each weight raised to pi_lo / (4K) first, then all scaled so that
+           their sum lies in [pi_lo, pi_hi] */
+        const double floor_ = (double)P->pi_lo / (4.0 * K);
+        double t = 0.0;
+        for (int q = 0; q < K; ++q) {
+          pis[q] = fmax(pis[q], floor_);
+          t += pis[q];
+        }
+        const double scale = fmin(fmax(t, (double)P->pi_lo), (double)P->pi_hi) / t;
+        for (int q = 0; q < K; ++q) pis[q] *= scale;
+      }
+      for (int q = 0; q < K; ++q) g[6 * q + 5] = pis[q];
+      g[6 * K] = sw;
+      g[6 * K + 1] = fmin(kk + 1.0, (double)P->k_max);
+      for (int c = 0; c < NC; ++c) gamma[c * pl + idx] = g[c];
+    }
+    free(T);
+  }
+}
+
 int32_t orc_num_threads(void) {
 #ifdef _OPENMP
   return (int32_t)omp_get_max_threads();
