@@ -227,6 +227,46 @@ pg_status pg_nll_backward(const pg_params *p, const pg_view *v, const pg_samples
 pg_status pg_estimate(const pg_params *p, const pg_view *v, const pg_samples *in, float *estimate,
                       void *stream);
 
+/* ---- K Gaussian lobes per pixel -------------------------------------------
+ * The mixture of Eq. (2) with K Gaussian lobes instead of one (Sec. 4.1 names
+ * the single lobe as the model's limit):
+ *   D(w) = sum_j pi_j N_j(M^-1 w)/(2 pi) + (1 - sum_j pi_j) p_b(w).
+ * Gamma is FP32 with 6K + 2 planes [6K+2][H*pitch]: lobe j at plane 6j holds
+ * (mu_x, mu_y, Sigma_xx, Sigma_xy, Sigma_yy, pi_j), then W and k.  1 <= K <=
+ * PG_MAX_LOBES.  Readings: a new model's lobes have Sigma = I/12, pi_init/K
+ * and means (0.5 + (j - (K-1)/2) / 4, 0.5); zeta selects lobe j when it lies
+ * in [c_j, c_j + pi_j) with c_j the sum of the earlier weights (the BRDF
+ * otherwise); every lobe mean is carried by reprojection (a new model when
+ * one falls below the horizon); each lobe is merged with its own evidence
+ * like the single lobe; unless PG_NO_CLAMP, every weight is raised to
+ * pi_lo/(4K) and all are scaled so that their sum lies in [pi_lo, pi_hi].
+ * The random words, the training set and the BRDF strategy are those of the
+ * single-lobe calls.  PG_EM_BATCH and PG_STALE_RESET are not supported
+ * (PG_ERR_UNSUPPORTED); lobes outside [1, PG_MAX_LOBES] is PG_ERR_ARG, and
+ * (6K + 2) * pitch * height must stay below 2^31 (PG_ERR_UNSUPPORTED). */
+#define PG_MAX_LOBES 4
+
+/* pg_reproject_sample with K lobes: out_gamma [6K+2][H*pitch] and the
+ * records (dir, pdf_mix, pdf_brdf, strategy; radiance untouched).
+ * prev and prev_gamma may be NULL only when frame == 0; prev must have
+ * cur's width, height and pitch; out_gamma must not alias prev_gamma. */
+pg_status pg_reproject_sample_lobes(const pg_params *p, int32_t lobes, const pg_view *cur,
+                                    const pg_view *prev, const float *prev_gamma, float *out_gamma,
+                                    const pg_samples *out, void *stream);
+
+/* pg_em_update (online) with K lobes, in place on gamma_inout
+ * [6K+2][H*pitch]: E-step posteriors gam_j = pi_j p_gj / D, per-lobe batch
+ * statistics, the stepwise merge of every lobe and the weight clamp.
+ * Reads samples->dir, pdf_brdf, strategy, radiance and the view's albedo. */
+pg_status pg_em_update_lobes(const pg_params *p, int32_t lobes, const pg_view *v, const pg_samples *in,
+                             float *gamma_inout, void *stream);
+
+/* pg_pdf with K lobes: pdf_mix = D for n_per_px directions per pixel
+ * (dir [3][n*H*pitch]); zero for pixels with omega_o below the surface and
+ * directions below the horizon. */
+pg_status pg_pdf_lobes(const pg_params *p, int32_t lobes, const pg_view *v, const float *gamma,
+                       int32_t n_per_px, const float *dir, float *pdf_mix, void *stream);
+
 /* ---- Batched frame: many views in two persistent launches ----------------
  * One frame of n views of any size and spp (Sec. 3.1 and Sec. 3.2 for each
  * view, with the light-field stand-in between them) as an upload of a packed

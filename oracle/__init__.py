@@ -89,7 +89,7 @@ def _declare(L):
     L.orc_reproject_k.argtypes = [P, i32, P, P, P, P, P, Rect]
     L.orc_sample_k.argtypes = [P, i32, P, P, i32, P, P, P, P, P, Rect]
     L.orc_pdf_k.argtypes = [P, i32, P, P, i32, P, P, Rect]
-    L.orc_em_k.argtypes = [P, i32, P, i32, P, P, P, P, P, Rect]
+    L.orc_em_k.argtypes = [P, i32, P, i32, P, P, P, P, P, P, Rect]
     L.orc_num_threads.restype = i32
 
 
@@ -397,16 +397,19 @@ def pdf_k(P, K, view, gamma, dirs, rect=None):
     return pmix
 
 
-def em_k(P, K, view, rec, gamma, rect=None):
+def em_k(P, K, view, rec, gamma, rect=None, with_stats=False):
+    """The updated K-lobe state; with with_stats also [K+1][H][W] holding B0
+    and each lobe's B1_j."""
     g = _f64(gamma).copy()
     assert g.shape[0] == 6 * K + 2
     spp = rec["strategy"].shape[0]
     d, pb = _f64(rec["dir"]), _f64(rec["pdf_brdf"])
     st = np.ascontiguousarray(rec["strategy"], dtype=np.uint8)
     L = _f64(rec["radiance"])
+    stats = np.zeros((K + 1,) + g.shape[1:]) if with_stats else None
     lib().orc_em_k(C.byref(P), K, C.byref(view.c), spp, _ptr(d), _ptr(pb), _ptr(st), _ptr(L), _ptr(g),
-                   _rect(view, rect))
-    return g
+                   _ptr(stats), _rect(view, rect))
+    return (g, stats) if with_stats else g
 
 
 def num_threads():

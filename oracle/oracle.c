@@ -1142,8 +1142,9 @@ void orc_reference(const orc_params *P, const orc_view *v, int32_t n_lights, con
  * State planes [6K + 2]: lobe j at 6j: (mu_x, mu_y, S_xx, S_xy, S_yy, pi_j),
  * then W and k.  Readings of this extension: a new model's lobes share
  * Sigma = I/12 and pi_init/K but start at distinct means
- * mu_j = (0.5 + 0.2 (j - (K-1)/2), 0.5) (identical lobes would stay
- * identical under EM); zeta picks lobe j when it falls in [c_j, c_j + pi_j)
+ * mu_j = (0.5 + (j - (K-1)/2) / 4, 0.5) (identical lobes would stay
+ * identical under EM; the means are dyadic, the same numbers in any
+ * precision); zeta picks lobe j when it falls in [c_j, c_j + pi_j)
  * with c_j the sum of the earlier pi, else the BRDF; each lobe is merged with
  * its own evidence B1_j like the single lobe; the clamp raises each weight to
  * at least pi_lo / (4K) (a lobe at zero weight would never gain evidence
@@ -1155,7 +1156,7 @@ static int nch_k(int K) { return 6 * K + 2; }
 static void reset_k(const orc_params *P, int K, double *g) {
   for (int j = 0; j < K; ++j) {
     double *l = g + 6 * j;
-    l[0] = 0.5 + 0.2 * (j - 0.5 * (K - 1));
+    l[0] = 0.5 + 0.25 * (j - 0.5 * (K - 1));
     l[1] = 0.5;
     l[2] = 1.0 / 12.0; l[3] = 0.0; l[4] = 1.0 / 12.0;
     l[5] = (double)P->pi_init / K;
@@ -1369,7 +1370,7 @@ void orc_pdf_k(const orc_params *P, int32_t K, const orc_view *v, const double *
  * evidence; then the weight clamp of the extension's reading. */
 void orc_em_k(const orc_params *P, int32_t K, const orc_view *v, int32_t spp, const double *dir,
               const double *pdf_brdf, const uint8_t *strategy, const double *radiance, double *gamma,
-              orc_rect r) {
+              double *stats, orc_rect r) {
   const int NC = nch_k(K);
   const int64_t pl = (int64_t)v->height * v->pitch;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -1378,6 +1379,8 @@ void orc_em_k(const orc_params *P, int32_t K, const orc_view *v, int32_t spp, co
     for (int x = r.x0; x < r.x1; ++x) {
       const int64_t idx = (int64_t)y * v->pitch + x;
       pixel_t px = load_pixel(P, v, idx);
+      if (stats)
+        for (int q = 0; q <= K; ++q) stats[q * pl + idx] = 0.0;
       if (!px.guided) continue;
       double g[6 * MAXK + 2];
       for (int c = 0; c < NC; ++c) g[c] = gamma[c * pl + idx];
@@ -1407,6 +1410,7 @@ void orc_em_k(const orc_params *P, int32_t K, const orc_view *v, int32_t spp, co
       }
       double B0 = 0.0;
       for (int j = 0; j < n; ++j) B0 += w[j];
+      if (stats) stats[idx] = B0;
       if (!(B0 > 0.0)) continue;
       const double eta = 1.0 / (kk + 1.0);
       const double sw = (1.0 - eta) * Wv + eta * B0;
@@ -1415,6 +1419,7 @@ void orc_em_k(const orc_params *P, int32_t K, const orc_view *v, int32_t spp, co
         double gq[MAX_SET], st[7];
         for (int j = 0; j < n; ++j) gq[j] = gam[j][q];
         orc_batch_stats(n, &u[0][0], w, gq, st);
+        if (stats) stats[(q + 1) * pl + idx] = st[1];
         double *l = g + 6 * q;
         const double so = (1.0 - eta) * l[5] * Wv, sn = eta * st[1], sg = so + sn;
         if (sg > 0.0 && st[1] > 0.0) {
@@ -1438,7 +1443,7 @@ void orc_em_k(const orc_params *P, int32_t K, const orc_view *v, int32_t spp, co
           pis[q] = fmax(pis[q], floor_);
           t += pis[q];
         }
-        const double scale = fmin(fmax(t, (double)P->pi_lo), (double)P->pi_hi) / t;
+        const double scale = t > 0.0 ? fmin(fmax(t, (double)P->pi_lo), (double)P->pi_hi) / t : 0.0;
         for (int q = 0; q < K; ++q) pis[q] *= scale;
       }
       for (int q = 0; q < K; ++q) g[6 * q + 5] = pis[q];

@@ -135,7 +135,8 @@ void orc_reference(const orc_params *P, const orc_view *v, int32_t n_lights, con
                    double ambient, const uint8_t *vis, int32_t n_samples, int64_t n_px, const int64_t *px_index,
                    double *mean, double *stderr_out);
 /* K Gaussian lobes per pixel (K <= 4): state planes [6K + 2] (per lobe
- * mu_x, mu_y, S_xx, S_xy, S_yy, pi_j; then W, k). */
+ * mu_x, mu_y, S_xx, S_xy, S_yy, pi_j; then W, k).  orc_em_k's stats (nullable)
+ * [K+1][H*pitch] receive B0 and each lobe's B1_j of the E-step. */
 void orc_reproject_k(const orc_params *P, int32_t K, const orc_view *cur, const orc_view *prev,
                      const double *gamma_prev, double *gamma_out, int32_t *src_index, orc_rect r);
 void orc_sample_k(const orc_params *P, int32_t K, const orc_view *v, const double *gamma, int32_t spp,
@@ -145,7 +146,7 @@ void orc_pdf_k(const orc_params *P, int32_t K, const orc_view *v, const double *
                const double *dirs, double *pdf_mix, orc_rect r);
 void orc_em_k(const orc_params *P, int32_t K, const orc_view *v, int32_t spp, const double *dir,
               const double *pdf_brdf, const uint8_t *strategy, const double *radiance, double *gamma,
-              orc_rect r);
+              double *stats, orc_rect r);
 int32_t orc_num_threads(void);
 
 #ifdef __cplusplus

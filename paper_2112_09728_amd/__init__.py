@@ -66,7 +66,9 @@ class PgBatchView(C.Structure):
 
 EXPORTS = ("pg_params_default", "pg_reproject", "pg_sample_mis", "pg_reproject_sample", "pg_pdf",
            "pg_light_field", "pg_em_update", "pg_nll_backward", "pg_estimate", "pg_batch_table_bytes",
-           "pg_batch_pack", "pg_frame_batched", "pg_philox", "pg_last_error")
+           "pg_batch_pack", "pg_frame_batched", "pg_reproject_sample_lobes", "pg_em_update_lobes",
+           "pg_pdf_lobes", "pg_philox", "pg_last_error")
+MAX_LOBES = 4
 
 _lib = None
 
@@ -96,6 +98,9 @@ def lib():
         L.pg_batch_table_bytes.argtypes = [C.c_int32]
         L.pg_batch_pack.argtypes = [P, C.c_int32, P, C.c_size_t]
         L.pg_frame_batched.argtypes = [P, P, C.c_size_t, P]
+        L.pg_reproject_sample_lobes.argtypes = [P, C.c_int32, P, P, P, P, P, P]
+        L.pg_em_update_lobes.argtypes = [P, C.c_int32, P, P, P, P]
+        L.pg_pdf_lobes.argtypes = [P, C.c_int32, P, P, C.c_int32, P, P, P]
         L.pg_philox.argtypes = [C.c_int32, P, C.c_uint64, P, P]
         L.pg_last_error.restype = C.c_char_p
         for name in EXPORTS[:-1]:
@@ -330,6 +335,60 @@ def frame_batched(host_table, device_table) -> None:
                                   _stream()), "pg_frame_batched")
 
 
+# ------------------------------------------------- K Gaussian lobes per pixel
+def new_lobes_gamma(lobes: int, height: int, width: int, device="cuda"):
+    """FP32 state of K lobes, [6K + 2][H][W]."""
+    import torch
+    return torch.zeros((6 * lobes + 2, height, width), dtype=torch.float32, device=device)
+
+
+def _lobes_state(t, lobes, name, view):
+    import torch
+    if t is None:
+        return None
+    _require(t, torch.float32, name)
+    want = (6 * lobes + 2, view.height, view.width)
+    if tuple(t.shape) != want:
+        raise ValueError(f"{name} must have shape {want} for {lobes} lobes, got {tuple(t.shape)}")
+    return _ptr(t)
+
+
+def _samples_fit(samples, view):
+    if (samples.height, samples.width) != (view.height, view.width):
+        raise ValueError(f"samples are {samples.height}x{samples.width}, the view {view.height}x{view.width}")
+
+
+def reproject_sample_lobes(p: PgParams, lobes: int, cur: View, prev: View | None, gamma_prev, gamma_out,
+                           samples: Samples):
+    _samples_fit(samples, cur)
+    if prev is not None and (prev.height, prev.width) != (cur.height, cur.width):
+        raise ValueError("prev must have cur's size")
+    _check(lib().pg_reproject_sample_lobes(C.byref(p), lobes, C.byref(cur.c),
+                                           None if prev is None else C.byref(prev.c),
+                                           _lobes_state(gamma_prev, lobes, "gamma_prev", cur),
+                                           _lobes_state(gamma_out, lobes, "gamma_out", cur), C.byref(samples.c),
+                                           _stream()), "pg_reproject_sample_lobes")
+
+
+def em_update_lobes(p: PgParams, lobes: int, view: View, samples: Samples, gamma):
+    _samples_fit(samples, view)
+    _check(lib().pg_em_update_lobes(C.byref(p), lobes, C.byref(view.c), C.byref(samples.c),
+                                    _lobes_state(gamma, lobes, "gamma", view), _stream()), "pg_em_update_lobes")
+
+
+def pdf_lobes(p: PgParams, lobes: int, view: View, gamma, dirs):
+    """D of the K-lobe mixture at directions dirs [3][n][H][W]."""
+    import torch
+    _require(dirs, torch.float32, "dirs")
+    n = dirs.shape[1]
+    if dirs.dim() != 4 or tuple(dirs.shape) != (3, n, view.height, view.width):
+        raise ValueError(f"dirs must have shape (3, n, {view.height}, {view.width}), got {tuple(dirs.shape)}")
+    pmix = torch.empty((n, view.height, view.width), dtype=torch.float32, device=dirs.device)
+    _check(lib().pg_pdf_lobes(C.byref(p), lobes, C.byref(view.c), _lobes_state(gamma, lobes, "gamma", view), n,
+                              _ptr(dirs), _ptr(pmix), _stream()), "pg_pdf_lobes")
+    return pmix
+
+
 def philox(counters, seed: int):
     """Philox4x32-10 words for device counters [n][4] (int32 tensor holding uint32 bits)."""
     import torch
@@ -340,4 +399,4 @@ def philox(counters, seed: int):
     return out
 
 
-from .guide import BatchedGuide, DeviceFrame, Guide, NLLFunction  # noqa: E402  (needs the names above)
+from .guide import BatchedGuide, DeviceFrame, Guide, LobesGuide, NLLFunction  # noqa: E402  (needs the names above)

@@ -1,0 +1,411 @@
+// K Gaussian lobes per pixel: the single lobe of the mixture of Eq. (2)
+// generalised to
+//   D(w) = sum_j pi_j N_j(M^-1 w) / (2 pi) + (1 - sum_j pi_j) p_b(w),
+// the limit of one Gaussian per pixel that Sec. 4.1 names lifted.  FP32
+// state of 6K + 2 planes: lobe j at plane 6j holds (mu_x, mu_y, S_xx, S_xy,
+// S_yy, pi_j), then W and k.
+//
+// Readings of the extension: a new model's lobes share Sigma = I/12 and
+// pi_init/K at the distinct means (0.5 + (j - (K-1)/2) / 4, 0.5); zeta selects
+// lobe j when it falls in [c_j, c_j + pi_j), c_j the sum of the earlier
+// weights, else the BRDF; each lobe is merged with its own evidence like the
+// single lobe; the clamp raises every weight to pi_lo/(4K) and scales them so
+// that their sum lies in [pi_lo, pi_hi]; reprojection carries every lobe mean
+// to the new hemisphere and starts a new model when any falls below it.
+//
+// Kernels: one lane per pixel.  The streaming pass (reprojection + sampling)
+// and the densities use the 64x4 XCD-banded tiles of the single-lobe path;
+// the training pass stages a tile's records with its 3-pixel halo in LDS
+// (the same staging and pick decoding as the single-lobe pass) and runs the
+// E-step of each pixel in its own lane, in natural order.
+#pragma once
+#include "pg_kernels.hpp"
+
+namespace pgk {
+
+constexpr int kMaxLobes = 4;
+
+template <int K>
+__device__ __forceinline__ void lobes_reset(const ParamsK &P, float g[6 * K + 2]) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    g[6 * j + 0] = 0.5f + 0.25f * ((float)j - 0.5f * (float)(K - 1));
+    g[6 * j + 1] = 0.5f;
+    g[6 * j + 2] = 1.0f / 12.0f;
+    g[6 * j + 3] = 0.0f;
+    g[6 * j + 4] = 1.0f / 12.0f;
+    g[6 * j + 5] = P.pi_init / (float)K;
+  }
+  g[6 * K] = 0.0f;
+  g[6 * K + 1] = 0.0f;
+}
+
+template <int K>
+__device__ __forceinline__ void lobes_load(const float *__restrict__ g, int plane, int idx, float out[6 * K + 2]) {
+#pragma unroll
+  for (int c = 0; c < 6 * K + 2; ++c) out[c] = g[c * plane + idx];
+}
+
+template <int K>
+__device__ __forceinline__ void lobes_store(float *__restrict__ g, int plane, int idx, const float in[6 * K + 2]) {
+#pragma unroll
+  for (int c = 0; c < 6 * K + 2; ++c) g[c * plane + idx] = in[c];
+}
+
+// Reprojection of one pixel (Sec. 3.1 with K lobes): the tests and the
+// source address of the single-lobe pass; every lobe mean keeps its world
+// direction across a change of normal.
+template <int K>
+__device__ __forceinline__ void lobes_reproject(const ParamsK &P, const ViewK &cur, const ViewK &prev,
+                                                const float *__restrict__ gprev, bool has_prev, int x, int y,
+                                                const PixelIn &pi, float g[6 * K + 2]) {
+  const int plane = cur.H * cur.pitch;
+  const int idx = y * cur.pitch + x;
+  const V3 n = pi.n;
+  const bool guided = dot3(n, pi.o) > 0.0f && pi.rough >= P.rough_min;
+  float zp = 0.0f, mx = 0.0f, my = 0.0f;
+  bool keep = has_prev && guided;
+  if (keep) {
+    zp = cur.z[idx];
+    if (cur.mv) {
+      mx = cur.mv[idx];
+      my = cur.mv[plane + idx];
+    }
+    if (cur.mask != nullptr && cur.mask[idx] != 0) keep = false;
+  }
+  int qx = 0, qy = 0;
+  if (keep) {
+    const float fx = ((float)x + 0.5f) - mx;
+    const float fy = ((float)y + 0.5f) - my;
+    if (fx >= 0.0f && fy >= 0.0f && fx < (float)prev.W && fy < (float)prev.H) {
+      qx = (int)floorf(fx);
+      qy = (int)floorf(fy);
+    } else {
+      keep = false;
+    }
+  }
+  if (keep) {
+    const int pplane = prev.H * prev.pitch;
+    const int qidx = qy * prev.pitch + qx;
+    const float zq = prev.z[qidx];
+    const V3 nq = load3(prev.n, pplane, qidx);
+    lobes_load<K>(gprev, pplane, qidx, g);
+    if (fabsf(zp - zq) > P.tau_z * zp) keep = false;
+    if (dot3(n, nq) < P.tau_n) keep = false;
+#pragma unroll
+    for (int c = 0; c < 6 * K + 2; ++c)
+      if (!isfinite(g[c])) keep = false;
+    if (keep && !(n.x == nq.x && n.y == nq.y && n.z == nq.z)) {
+      const Frame fq = make_frame(nq);
+      const Frame fp = make_frame(n);
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const V3 lq = sq2hemi(fminf(fmaxf(g[6 * j], 0.0f), 1.0f), fminf(fmaxf(g[6 * j + 1], 0.0f), 1.0f));
+        const V3 lp = to_local(fp, to_world(fq, lq));
+        if (lp.z <= 0.0f)
+          keep = false;
+        else
+          hemi2sq(normalized(lp), g[6 * j], g[6 * j + 1]);
+      }
+    }
+  }
+  if (!keep) lobes_reset<K>(P, g);
+}
+
+// Sampling of one pixel with the K-lobe mixture: the random words and the
+// BRDF strategy of the single-lobe pass; a guided draw takes the lobe that
+// zeta selects.  Every density is taken at the drawn direction.
+template <int K>
+__device__ __forceinline__ void lobes_sample(const ParamsK &P, const ViewK &v, const SamplesK &S, int x, int y,
+                                             const PixelIn &pi, const float g[6 * K + 2]) {
+  const int plane = v.H * v.pitch;
+  const int splane = S.spp * plane;
+  const bool valid = dot3(pi.n, pi.o) > 0.0f;
+  const bool guided = valid && pi.rough >= P.rough_min && g[6 * K + 1] >= 1.0f;
+  const Pixel px = make_pixel(P, pi.n, pi.o, pi.rough, 0.0f);
+  Gauss G[K];
+  float w[K], tot = 0.0f;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    G[j] = gauss_setup(g[6 * j], g[6 * j + 1], g[6 * j + 2], g[6 * j + 3], g[6 * j + 4], P.eps);
+    w[j] = guided ? g[6 * j + 5] : 0.0f;
+    tot += w[j];
+  }
+  const uint32_t pix = (uint32_t)(y * v.W + x);
+  for (int s = 0; s < S.spp; ++s) {
+    const int rec = (s * v.H + y) * v.pitch + x;
+    uint8_t code = 0;
+    V3 l = V3{0.0f, 0.0f, 0.0f};
+    float D = 0.0f, pb = 0.0f;
+    if (valid) {
+      const uint4 w4 = philox4x32_10(pix, P.frame, (uint32_t)s, P.view, P.key0, P.key1);
+      const float zeta = u24(w4.x), xl = u24(w4.y), x1 = u24(w4.z), x2 = u24(w4.w);
+      float sn, cs;
+      sincospi_small(2.0f * x2, &sn, &cs);
+      // the lobe zeta selects (-1: the BRDF)
+      int lobe = -1;
+      float c = 0.0f;
+      float gmx = 0.0f, gmy = 0.0f, gl11 = 0.0f, gl21 = 0.0f, gl22 = 0.0f;
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const float cn = c + w[j];
+        if (lobe < 0 && zeta >= c && zeta < cn) {
+          lobe = j;
+          gmx = G[j].mx;
+          gmy = G[j].my;
+          gl11 = G[j].l11;
+          gl21 = G[j].l21;
+          gl22 = G[j].l22;
+        }
+        c = cn;
+      }
+      bool ok;
+      if (lobe >= 0) {
+        const float rho = fsqrt(-1.38629436f * __builtin_amdgcn_logf(1.0f - x1));
+        const float z1 = rho * cs, z2 = rho * sn;
+        const float ux = fmaf(gl11, z1, gmx);
+        const float uy = fmaf(gl22, z2, fmaf(gl21, z1, gmy));
+        ok = ux >= 0.0f && ux <= 1.0f && uy >= 0.0f && uy <= 1.0f;
+        if (ok) l = sq2hemi(ux, uy);
+        code = ok ? 2 : 3;
+      } else {
+        if (xl < P.s_d) {
+          const float r = fsqrt(x1);
+          l = V3{r * cs, r * sn, fsqrt(1.0f - x1)};
+          ok = l.z > 0.0f;
+        } else {
+          const float t2 = px.alpha2 * x1 * frcp(1.0f - x1);
+          const float ch = __builtin_amdgcn_rsqf(1.0f + t2);
+          const float sh = fsqrt(t2) * ch;
+          const V3 h = V3{sh * cs, sh * sn, ch};
+          const float woh = dot3(px.wo, h);
+          l = V3{2.0f * woh * h.x - px.wo.x, 2.0f * woh * h.y - px.wo.y, 2.0f * woh * h.z - px.wo.z};
+          ok = l.z > 0.0f && woh > 0.0f;
+        }
+        code = ok ? 1 : 4;
+      }
+      if (ok && l.z > 0.0f) {  // a guided draw on the rim has no density
+        pb = brdf_pdf_only(px, l);
+        D = (1.0f - tot) * pb;
+        if (guided) {
+          float ux, uy;
+          hemi2sq(l, ux, uy);
+#pragma unroll
+          for (int j = 0; j < K; ++j) D = fmaf(w[j], gauss_pdf_fast(G[j], ux, uy), D);
+        }
+      }
+    }
+    V3 wd = V3{0.0f, 0.0f, 0.0f};
+    if (code == 1 || code == 2) {
+      wd = to_world(px.f, l);
+    } else {
+      D = 0.0f;
+      pb = 0.0f;
+    }
+    S.dir[rec] = wd.x;
+    S.dir[splane + rec] = wd.y;
+    S.dir[2 * splane + rec] = wd.z;
+    S.pmix[rec] = D;
+    S.pb[rec] = pb;
+    S.strat[rec] = code;
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_lobes_reproject_sample(ParamsK P, ViewK cur, ViewK prev,
+                                                                const float *__restrict__ gprev,
+                                                                float *__restrict__ gout, SamplesK S, int has_prev) {
+  int x, y;
+  stream_xy(cur.W, cur.H, x, y);
+  if (x >= cur.W || y >= cur.H) return;
+  const int idx = y * cur.pitch + x;
+  const PixelIn pi = load_pixel(cur, idx);
+  float g[6 * K + 2];
+  lobes_reproject<K>(P, cur, prev, gprev, has_prev != 0, x, y, pi, g);
+  lobes_sample<K>(P, cur, S, x, y, pi, g);
+  lobes_store<K>(gout, cur.H * cur.pitch, idx, g);
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_lobes_pdf(ParamsK P, ViewK v, const float *__restrict__ gamma, int n_per_px,
+                                                   const float *__restrict__ dir, float *__restrict__ pmix) {
+  int x, y;
+  stream_xy(v.W, v.H, x, y);
+  if (x >= v.W || y >= v.H) return;
+  const int plane = v.H * v.pitch;
+  const int idx = y * v.pitch + x;
+  const int dplane = n_per_px * plane;
+  float g[6 * K + 2];
+  lobes_load<K>(gamma, plane, idx, g);
+  const PixelIn pi = load_pixel(v, idx);
+  const bool valid = dot3(pi.n, pi.o) > 0.0f;
+  const bool guided = valid && pi.rough >= P.rough_min && g[6 * K + 1] >= 1.0f;
+  const Pixel px = make_pixel(P, pi.n, pi.o, pi.rough, 0.0f);
+  float tot = 0.0f;
+#pragma unroll
+  for (int j = 0; j < K; ++j) tot += guided ? g[6 * j + 5] : 0.0f;
+  for (int s = 0; s < n_per_px; ++s) {
+    const int r = (s * v.H + y) * v.pitch + x;
+    const V3 w = V3{dir[r], dir[dplane + r], dir[2 * dplane + r]};
+    float D = 0.0f;
+    if (valid && dot3(w, w) > 0.0f) {
+      const V3 l = to_local(px.f, normalized(w));
+      if (l.z > 0.0f) {
+        D = (1.0f - tot) * brdf_pdf_only(px, l);
+        if (guided) {
+          float ux, uy;
+          hemi2sq(l, ux, uy);
+#pragma unroll
+          for (int j = 0; j < K; ++j) {
+            const Gauss G = gauss_setup(g[6 * j], g[6 * j + 1], g[6 * j + 2], g[6 * j + 3], g[6 * j + 4], P.eps);
+            D = fmaf(g[6 * j + 5], gauss_pdf_acc(G, ux, uy), D);
+          }
+        }
+      }
+    }
+    pmix[r] = D;
+  }
+}
+
+// E-step of one training record for K lobes: posterior gam_j = pi_j p_gj / D
+// under the model's weights, and the per-lobe running sums of em_visit.
+template <int K>
+struct LobesCtx {
+  Pixel px;
+  Gauss G[K];
+  float pi[K], one_m_tot;
+};
+
+template <int K>
+__device__ __forceinline__ void lobes_visit(const LobesCtx<K> &c, float4 r, float &B0, Accum a[K]) {
+  if (r.w == 0.0f) return;
+  const V3 l = to_local(c.px.f, V3{r.x, r.y, r.z});
+  if (l.z <= 0.0f) return;
+  float ux, uy, f, pb;
+  hemi2sq(l, ux, uy);
+  brdf_eval(c.px, l, f, pb);
+  const float w = r.w * f * l.z;
+  float ga[K], D = c.one_m_tot * pb;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    ga[j] = c.pi[j] * gauss_pdf_fast(c.G[j], ux, uy);
+    D += ga[j];
+  }
+  const float rD = __builtin_amdgcn_rcpf(fmaxf(D, 1.17549435e-38f));
+  B0 += w;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const float vw = w * (ga[j] * rD);
+    if (vw >= 1.17549435e-38f) {
+      const float bn = a[j].B1 + vw;
+      const float rb = __builtin_amdgcn_rcpf(bn);
+      const float fr = vw * rb, keep = a[j].B1 * rb;
+      a[j].B1 = bn;
+      const float dx = ux - a[j].mx, dy = uy - a[j].my;
+      a[j].mx = fmaf(dx, fr, a[j].mx);
+      a[j].my = fmaf(dy, fr, a[j].my);
+      const float fx = fr * dx, fy = fr * dy;
+      a[j].sxx = keep * fmaf(fx, dx, a[j].sxx);
+      a[j].sxy = keep * fmaf(fx, dy, a[j].sxy);
+      a[j].syy = keep * fmaf(fy, dy, a[j].syy);
+    }
+  }
+}
+
+// Training pass with K lobes (Sec. 3.2, Sec. 4.2): the records of a TW x TH
+// tile and its halo staged in LDS, then each pixel's training set (own
+// samples, then N(k) picks of stream 1) visited from LDS in the order of the
+// oracle, and the stepwise merge of every lobe.
+// Dynamic LDS: records [spp][SH][SW] float4.
+template <int K, int TW, int TH>
+__global__ __launch_bounds__(TW *TH) void k_lobes_em(ParamsK P, ViewK v, SamplesK S, float *__restrict__ gamma,
+                                                     int tiles_x, int n_tiles) {
+  constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH;
+  extern __shared__ float4 lds[];
+  const int tile = xcd_tile(blockIdx.x, n_tiles);
+  const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
+  stage_records<TW, TH>(v, S, lds, tx0, ty0, 0);
+  __syncthreads();
+  const int lx = (int)threadIdx.x % TW, ly = (int)threadIdx.x / TW;
+  const int x = tx0 + lx, y = ty0 + ly;
+  if (x >= v.W || y >= v.H) return;  // no barrier follows
+  const int plane = v.H * v.pitch;
+  const int idx = y * v.pitch + x;
+  const PixelIn pin = load_pixel(v, idx);
+  if (!(dot3(pin.n, pin.o) > 0.0f && pin.rough >= P.rough_min)) return;
+  float g[6 * K + 2];
+  lobes_load<K>(gamma, plane, idx, g);
+  LobesCtx<K> c;
+  c.px = make_pixel(P, pin.n, pin.o, pin.rough, v.alb[idx]);
+  float tot = 0.0f;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    c.G[j] = gauss_setup(g[6 * j], g[6 * j + 1], g[6 * j + 2], g[6 * j + 3], g[6 * j + 4], P.eps);
+    c.pi[j] = g[6 * j + 5];
+    tot += c.pi[j];
+  }
+  c.one_m_tot = 1.0f - tot;
+  float B0 = 0.0f;
+  Accum a[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) a[j] = Accum{0, 0, 0, 0, 0, 0, 0};
+  const int spp = S.spp;
+  const int own = (ly + kR) * SW + (lx + kR);
+  for (int s = 0; s < spp; ++s) lobes_visit<K>(c, lds[s * SA + own], B0, a);
+  const int npick = n_picks(P, (int)g[6 * K + 1]);
+  const uint32_t cs = (uint32_t)(kCand * spp);
+  const uint32_t inv_spp = (65536u + (uint32_t)spp - 1u) / (uint32_t)spp;
+  const uint32_t pix = (uint32_t)(y * v.W + x);
+  for (int m0 = 0; m0 < npick; m0 += 8) {
+    const uint4 w4 = philox4x32_10(pix, P.frame, (1u << 16) | (uint32_t)(m0 >> 3), P.view, P.key0, P.key1);
+    float4 r[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r[j] = lds[pick_entry<SA, SW>(w4, j, cs, inv_spp, (uint32_t)spp, own)];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (m0 + j < npick) lobes_visit<K>(c, r[j], B0, a);
+  }
+  if (!(B0 > 0.0f)) return;  // no training sample: the model stays as it is
+  const float Wv = g[6 * K], kk = g[6 * K + 1];
+  const float eta = frcp(kk + 1.0f);
+  const float sw = fmaf(1.0f - eta, Wv, eta * B0);
+  const float isw = 1.0f / sw;
+  float pn[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    float *l = g + 6 * j;
+    const float so = (1.0f - eta) * l[5] * Wv;
+    const float sn = eta * a[j].B1;
+    const float sg = so + sn;
+    if (sg > 0.0f && a[j].B1 > 0.0f) {
+      const float al = so / sg, be = sn / sg;
+      const float dx = l[0] - a[j].mx, dy = l[1] - a[j].my;
+      const float ab = al * be;
+      l[0] = fmaf(al, l[0], be * a[j].mx);
+      l[1] = fmaf(al, l[1], be * a[j].my);
+      l[2] = fmaf(ab * dx, dx, fmaf(al, l[2], be * a[j].sxx));
+      l[3] = fmaf(ab * dx, dy, fmaf(al, l[3], be * a[j].sxy));
+      l[4] = fmaf(ab * dy, dy, fmaf(al, l[4], be * a[j].syy));
+    }
+    pn[j] = sg * isw;
+  }
+  if (!(P.flags & kNoClamp)) {
+    const float fl = P.pi_lo * (0.25f / (float)K);
+    float t = 0.0f;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      pn[j] = fmaxf(pn[j], fl);
+      t += pn[j];
+    }
+    const float scale = t > 0.0f ? fminf(fmaxf(t, P.pi_lo), P.pi_hi) / t : 0.0f;
+#pragma unroll
+    for (int j = 0; j < K; ++j) pn[j] *= scale;
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) g[6 * j + 5] = pn[j];
+  g[6 * K] = sw;
+  g[6 * K + 1] = fminf(kk + 1.0f, (float)P.k_max);
+  lobes_store<K>(gamma, plane, idx, g);
+}
+
+}  // namespace pgk

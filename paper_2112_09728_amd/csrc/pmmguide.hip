@@ -12,6 +12,7 @@
 #include <type_traits>
 
 #include "pg_kernels.hpp"
+#include "pg_lobes.hpp"
 #include "pmmguide.h"
 
 using namespace pgk;
@@ -366,6 +367,26 @@ pg_status class_tile(const pg_params *p, int spp, Tile &t) {
   return ok();
 }
 
+pg_status check_lobes(const pg_params *p, int32_t lobes, const pg_view *v) {
+  if (lobes < 1 || lobes > kMaxLobes) return fail(PG_ERR_ARG, "lobes %d outside [1, %d]", lobes, kMaxLobes);
+  if (p->flags & (PG_EM_BATCH | PG_STALE_RESET))
+    return fail(PG_ERR_UNSUPPORTED, "PG_EM_BATCH and PG_STALE_RESET are not built for K lobes");
+  if ((int64_t)v->pitch * v->height * (6 * lobes + 2) >= ((int64_t)1 << 31))
+    return fail(PG_ERR_UNSUPPORTED, "(6K + 2) * pitch * height too large for 32-bit indexing");
+  return PG_OK;
+}
+
+// Calls f with std::integral_constant<int, K> for K = lobes (checked before).
+template <typename F>
+pg_status dispatch_lobes(int lobes, F &&f) {
+  switch (lobes) {
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 3: return f(std::integral_constant<int, 3>{});
+    default: return f(std::integral_constant<int, 4>{});
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -535,6 +556,82 @@ pg_status pg_estimate(const pg_params *p, const pg_view *v, const pg_samples *in
   const SamplesK S = to_k(in);
   hipLaunchKernelGGL(k_estimate, stream_grid(V.W, V.H), dim3(64, 4), 0, (hipStream_t)stream, P, V, S, estimate);
   return check_launch("pg_estimate");
+}
+
+pg_status pg_reproject_sample_lobes(const pg_params *p, int32_t lobes, const pg_view *cur, const pg_view *prev,
+                                    const float *prev_gamma, float *out_gamma, const pg_samples *out, void *stream) {
+  pg_status st;
+  if ((st = check_params(p)) || (st = check_view(cur, "cur", false)) || (st = check_lobes(p, lobes, cur)) ||
+      (st = check_samples(out, true, false)))
+    return st;
+  if (!out_gamma) return fail(PG_ERR_ARG, "out_gamma is NULL");
+  const bool has_prev = p->frame > 0;
+  if (has_prev) {
+    if ((st = check_view(prev, "prev", false))) return st;
+    if (!prev_gamma) return fail(PG_ERR_ARG, "prev_gamma is NULL");
+    if (prev_gamma == out_gamma) return fail(PG_ERR_ARG, "prev_gamma aliases out_gamma");
+    if (prev->width != cur->width || prev->height != cur->height || prev->pitch != cur->pitch)
+      return fail(PG_ERR_UNSUPPORTED, "prev must have cur's width, height and pitch");
+  }
+  const ParamsK P = to_k(p);
+  const ViewK C = to_k(cur);
+  const ViewK Q = has_prev ? to_k(prev) : C;
+  const SamplesK S = to_k(out);
+  hipStream_t s = (hipStream_t)stream;
+  return dispatch_lobes(lobes, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    hipLaunchKernelGGL((k_lobes_reproject_sample<K>), stream_grid(C.W, C.H), dim3(64, 4), 0, s, P, C, Q,
+                       has_prev ? prev_gamma : out_gamma, out_gamma, S, has_prev ? 1 : 0);
+    return check_launch("pg_reproject_sample_lobes");
+  });
+}
+
+pg_status pg_em_update_lobes(const pg_params *p, int32_t lobes, const pg_view *v, const pg_samples *in,
+                             float *gamma_inout, void *stream) {
+  pg_status st;
+  if ((st = check_params(p)) || (st = check_view(v, "view", true)) || (st = check_lobes(p, lobes, v)) ||
+      (st = check_samples(in, false, true)))
+    return st;
+  if (!gamma_inout) return fail(PG_ERR_ARG, "gamma is NULL");
+  const ParamsK P = to_k(p);
+  const ViewK V = to_k(v);
+  const SamplesK S = to_k(in);
+  hipStream_t s = (hipStream_t)stream;
+  // 32x8 tiles, 32x4 above 4 spp (the records of 8 planes and the halo fit
+  // 64 KiB)
+  const int TH = in->spp > 4 ? 4 : 8;
+  const int tx = (V.W + 31) / 32, ty = (V.H + TH - 1) / TH;
+  const size_t lds = (size_t)in->spp * (32 + 2 * kR) * (TH + 2 * kR) * sizeof(float4);
+  return dispatch_lobes(lobes, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    if (TH == 8)
+      hipLaunchKernelGGL((k_lobes_em<K, 32, 8>), dim3(tx * ty), dim3(256), lds, s, P, V, S, gamma_inout, tx,
+                         tx * ty);
+    else
+      hipLaunchKernelGGL((k_lobes_em<K, 32, 4>), dim3(tx * ty), dim3(128), lds, s, P, V, S, gamma_inout, tx,
+                         tx * ty);
+    return check_launch("pg_em_update_lobes");
+  });
+}
+
+pg_status pg_pdf_lobes(const pg_params *p, int32_t lobes, const pg_view *v, const float *gamma, int32_t n_per_px,
+                       const float *dir, float *pdf_mix, void *stream) {
+  pg_status st;
+  if ((st = check_params(p)) || (st = check_view(v, "view", false)) || (st = check_lobes(p, lobes, v))) return st;
+  if (!gamma) return fail(PG_ERR_ARG, "gamma is NULL");
+  if (n_per_px < 1 || n_per_px > 64) return fail(PG_ERR_ARG, "n_per_px %d outside [1, 64]", n_per_px);
+  if ((int64_t)v->pitch * v->height * n_per_px * 3 >= ((int64_t)1 << 31))
+    return fail(PG_ERR_UNSUPPORTED, "n_per_px * pitch * height too large for 32-bit indexing");
+  if (!dir || !pdf_mix) return fail(PG_ERR_ARG, "dir and pdf_mix are required");
+  const ParamsK P = to_k(p);
+  const ViewK V = to_k(v);
+  hipStream_t s = (hipStream_t)stream;
+  return dispatch_lobes(lobes, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    hipLaunchKernelGGL((k_lobes_pdf<K>), stream_grid(V.W, V.H), dim3(64, 4), 0, s, P, V, gamma, n_per_px, dir,
+                       pdf_mix);
+    return check_launch("pg_pdf_lobes");
+  });
 }
 
 size_t pg_batch_table_bytes(int32_t n_views) { return n_views < 1 ? 0 : batch_bytes(n_views); }

@@ -3,7 +3,8 @@
 ``Guide`` owns the per-view device state (two Gamma buffers used in turn, the
 sample records) and runs one frame of the path: reprojection and sampling
 (fused, or as two calls), the analytic light field that stands in for the
-trace, and the EM update.  ``BatchedGuide`` does the same for many views at
+trace, and the EM update; ``LobesGuide`` the same with K Gaussian lobes per
+pixel.  ``BatchedGuide`` does the same for many views at
 once through pg_frame_batched, eagerly or by replaying captured graphs, and
 picks its training tile by timing the candidates.  ``NLLFunction`` puts the
 hand-written adjoint of the radiance-weighted mixture NLL behind
@@ -14,8 +15,8 @@ from __future__ import annotations
 import torch
 
 from . import (PgBatchView, PgParams, Samples, View, _gamma, batch_pack, batch_table_bytes, em_update,
-               frame_batched, light_field, lights_struct, new_gamma, params, reproject, reproject_sample,
-               sample_mis, nll_backward)
+               em_update_lobes, frame_batched, light_field, lights_struct, new_gamma, new_lobes_gamma, params,
+               reproject, reproject_sample, reproject_sample_lobes, sample_mis, nll_backward)
 
 TILES = ((32, 8), (16, 16), (64, 4), (32, 4), (16, 8), (64, 2), (32, 16), (64, 8))
 
@@ -75,6 +76,30 @@ class Guide:
             sample_mis(p, cur.view, g_out, self.samples)
         light_field(self.lights, cur.view, cur.vis, self.samples)
         em_update(p, cur.view, self.samples, g_out)
+        self.cur = 1 - self.cur
+        self.frame = t + 1
+        return g_out
+
+
+class LobesGuide(Guide):
+    """Guide with K Gaussian lobes per pixel (FP32 state [6K + 2][H][W]):
+    reprojection + sampling, the light field and the K-lobe EM update."""
+
+    def __init__(self, width: int, height: int, lights, ambient, lobes: int = 2, spp: int = 1, seed: int = 0,
+                 view_id: int = 0, device="cuda", **param_overrides):
+        super().__init__(width, height, lights, ambient, spp=spp, seed=seed, view_id=view_id, device=device,
+                         **param_overrides)
+        self.lobes = lobes
+        self.gamma = [new_lobes_gamma(lobes, height, width, device), new_lobes_gamma(lobes, height, width, device)]
+
+    def step(self, cur: DeviceFrame, prev: DeviceFrame | None, frame: int | None = None):
+        t = self.frame if frame is None else frame
+        p = self.params(t)
+        pv = prev.view if (prev is not None and t > 0) else None
+        g_prev, g_out = self.gamma[self.cur], self.gamma[1 - self.cur]
+        reproject_sample_lobes(p, self.lobes, cur.view, pv, g_prev if t > 0 else None, g_out, self.samples)
+        light_field(self.lights, cur.view, cur.vis, self.samples)
+        em_update_lobes(p, self.lobes, cur.view, self.samples, g_out)
         self.cur = 1 - self.cur
         self.frame = t + 1
         return g_out

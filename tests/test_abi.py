@@ -121,6 +121,46 @@ def test_argument_errors_before_launch():
     assert pg.lib().pg_last_error().decode() == ""
 
 
+@no_device
+def test_lobes_argument_errors_before_launch():
+    L = pg.lib()
+    P = pg.params(1, frame=1)
+    v = _view()
+    s = _samples()
+    big = _view(w=16384, h=5100)   # 26 planes pass 2^31 at K = 4 (24 do not)
+    other = _view(w=9)
+    cases = [
+        (L.pg_em_update_lobes, (C.byref(P), 0, C.byref(v), C.byref(s), FAKE, None), pg.PG_ERR_ARG),
+        (L.pg_em_update_lobes, (C.byref(P), 5, C.byref(v), C.byref(s), FAKE, None), pg.PG_ERR_ARG),
+        (L.pg_em_update_lobes, (C.byref(P), 2, C.byref(v), C.byref(s), None, None), pg.PG_ERR_ARG),
+        (L.pg_em_update_lobes, (C.byref(P), 2, C.byref(_view(albedo=False)), C.byref(s), FAKE, None),
+         pg.PG_ERR_ARG),
+        (L.pg_em_update_lobes, (C.byref(pg.params(1, flags=pg.PG_EM_BATCH)), 2, C.byref(v), C.byref(s), FAKE,
+                                None), pg.PG_ERR_UNSUPPORTED),
+        (L.pg_em_update_lobes, (C.byref(pg.params(1, flags=pg.PG_STALE_RESET)), 2, C.byref(v), C.byref(s),
+                                FAKE, None), pg.PG_ERR_UNSUPPORTED),
+        (L.pg_em_update_lobes, (C.byref(P), 4, C.byref(big), C.byref(s), FAKE, None), pg.PG_ERR_UNSUPPORTED),
+        (L.pg_reproject_sample_lobes, (C.byref(P), 2, C.byref(v), C.byref(v), FAKE, FAKE, C.byref(s), None),
+         pg.PG_ERR_ARG),
+        (L.pg_reproject_sample_lobes, (C.byref(P), 2, C.byref(v), None, FAKE, FAKE + 4096, C.byref(s), None),
+         pg.PG_ERR_ARG),
+        (L.pg_reproject_sample_lobes, (C.byref(P), 2, C.byref(v), C.byref(v), None, FAKE, C.byref(s), None),
+         pg.PG_ERR_ARG),
+        (L.pg_reproject_sample_lobes, (C.byref(P), 2, C.byref(v), C.byref(other), FAKE, FAKE + 4096,
+                                       C.byref(s), None), pg.PG_ERR_UNSUPPORTED),
+        (L.pg_reproject_sample_lobes, (C.byref(P), 2, C.byref(v), C.byref(v), FAKE, None, C.byref(s), None),
+         pg.PG_ERR_ARG),
+        (L.pg_pdf_lobes, (C.byref(P), 2, C.byref(v), FAKE, 0, FAKE, FAKE, None), pg.PG_ERR_ARG),
+        (L.pg_pdf_lobes, (C.byref(P), 2, C.byref(v), FAKE, 1, None, FAKE, None), pg.PG_ERR_ARG),
+        (L.pg_pdf_lobes, (C.byref(P), 2, C.byref(v), None, 1, FAKE, FAKE, None), pg.PG_ERR_ARG),
+        (L.pg_pdf_lobes, (C.byref(P), -1, C.byref(v), FAKE, 1, FAKE, FAKE, None), pg.PG_ERR_ARG),
+    ]
+    for fn, args, want in cases:
+        st, msg = _status(fn, *args)
+        assert st == want, (fn.__name__, st, msg)
+        assert msg, fn.__name__
+
+
 def test_pick_division_identity():
     """The training kernel divides a pick code c < 48 spp by spp as
     (c * ceil(2^16/spp)) >> 16; exact for every code it can meet."""
