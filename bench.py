@@ -90,6 +90,8 @@ def parse():
                     help="budget of the oracle timing on the host (0 = skip)")
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--tile", default=None, help="training tile WxH (default: the library's)")
+    ap.add_argument("--lobes", type=int, default=1,
+                    help="Gaussian lobes per pixel; above 1 the K-lobe calls run (FP32 state, fused)")
     ap.add_argument("--workload", default="1080p", choices=["1080p", "batched16"],
                     help="1080p: the single-view path (default); batched16: 16 uneven views, "
                          "FP16 Gamma, batched frame (eager and graph-replayed) against 16 plain "
@@ -117,8 +119,12 @@ def main():
     cfg = wl.CONFIGS["1080p_spp1_64f_fp32_pan"]
     seed = cfg["seed"] if a.seed is None else a.seed
     W, H, S = a.width, a.height, a.spp
+    K = a.lobes
+    if K != 1 and (a.gamma_dtype != "f32" or a.unfused or a.tile):
+        print("bench.py: the K-lobe calls take an FP32 state, fused, with their own tile", file=sys.stderr)
+        sys.exit(2)
     dt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[a.gamma_dtype]
-    G = 32 if a.gamma_dtype == "f32" else 16
+    G = (32 if a.gamma_dtype == "f32" else 16) if K == 1 else 4 * (6 * K + 2)
     frames = a.warmup + a.steps
     t0 = time.time()
     seq = wl.Sequence(W, H, seed, moving=True)
@@ -131,8 +137,11 @@ def main():
     over = {}
     if a.tile:
         over["tile_w"], over["tile_h"] = (int(v) for v in a.tile.lower().split("x"))
-    guide = pg.Guide(W, H, lights, ambient, spp=S, seed=seed, gamma_dtype=dt, fused=not a.unfused,
-                     **over)
+    if K == 1:
+        guide = pg.Guide(W, H, lights, ambient, spp=S, seed=seed, gamma_dtype=dt, fused=not a.unfused,
+                         **over)
+    else:
+        guide = pg.LobesGuide(W, H, lights, ambient, lobes=K, spp=S, seed=seed)
     torch.cuda.synchronize()
     print(f"bench: setup {time.time() - t0:.1f} s ({W}x{H}, spp {S}, Gamma {a.gamma_dtype}, "
           f"{frames} frames resident on the device)", file=sys.stderr, flush=True)
@@ -144,7 +153,9 @@ def main():
         g_prev, g_out = guide.gamma[guide.cur], guide.gamma[1 - guide.cur]
         if ev is not None:
             ev[0].record()
-        if a.unfused:
+        if K > 1:
+            pg.reproject_sample_lobes(p, K, cur, prev, g_prev if t else None, g_out, guide.samples)
+        elif a.unfused:
             pg.reproject(p, cur, prev, g_prev if t else None, g_out)
             pg.sample_mis(p, cur, g_out, guide.samples)
         else:
@@ -154,7 +165,10 @@ def main():
         pg.light_field(guide.lights, cur, dev_frames[t].vis, guide.samples)
         if ev is not None:
             ev[2].record()
-        pg.em_update(p, cur, guide.samples, g_out)
+        if K > 1:
+            pg.em_update_lobes(p, K, cur, guide.samples, g_out)
+        else:
+            pg.em_update(p, cur, guide.samples, g_out)
         if ev is not None:
             ev[3].record()
         guide.cur = 1 - guide.cur
@@ -196,14 +210,19 @@ def main():
     # measured HBM traffic and VALU counts of the dominant kernel, from the
     # committed rocprofv3 summaries of this workload (null when the kernel
     # sources have changed since, or for another workload)
-    default = (W, H, S, a.gamma_dtype, a.tile, a.unfused) == (1920, 1080, 1, "f32", None, False)
-    dom_name = "k_em" if dominant == "em" else "k_reproject_sample"
+    # summaries exist for the default workload at 1 and 2 lobes
+    default = (W, H, S, a.gamma_dtype, a.tile, a.unfused) == (1920, 1080, 1, "f32", None, False) and K in (1, 2)
+    tag = "" if K == 1 else f"_k{K}"
+    if K == 1:
+        dom_name = "k_em" if dominant == "em" else "k_reproject_sample"
+    else:
+        dom_name = "k_lobes_em" if dominant == "em" else "k_lobes_reproject_sample"
     traffic = alu = None
     if default:
-        row = profile_row("path_1080p_spp1_pan_traffic.md", dom_name)
+        row = profile_row(f"path_1080p_spp1_pan{tag}_traffic.md", dom_name)
         if row:
             traffic = round((float(row[3]) + float(row[4])) * 1e6)
-        row = profile_row("path_1080p_spp1_pan_sq_counters.md", dom_name)
+        row = profile_row(f"path_1080p_spp1_pan{tag}_sq_counters.md", dom_name)
         if row:
             lane_ops = float(row[1]) * float(row[2]) * 64
             us = float((em if dominant == "em" else rs).mean()) * 1e3
@@ -212,7 +231,7 @@ def main():
                    "achieved": round(ach / 1e12, 2), "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2), "unit": "T lane-op/s",
                    "frac": round(ach / VALU_PEAK_LANE_OPS, 4), "valu_per_wave": float(row[2])}
     gk = guide.state
-    kmean = float(gk[7].float().mean())
+    kmean = float(gk[-1].float().mean())
     print(f"bench: per frame reproject+sample {rs.mean() * 1e3:.1f} us, light {lf.mean() * 1e3:.1f} us, "
           f"EM {em.mean() * 1e3:.1f} us (first timed {em[0] * 1e3:.1f}, last {em[-1] * 1e3:.1f}); "
           f"wall {total_ms / a.steps * 1e3:.1f} us/frame; mean k at end {kmean:.2f}",
@@ -220,7 +239,7 @@ def main():
 
     cpu = None
     if a.cpu_baseline_seconds > 0:
-        cpu = cpu_baseline(seed, S, W, H, a.cpu_baseline_seconds)
+        cpu = cpu_baseline(seed, S, W, H, a.cpu_baseline_seconds, K)
 
     out = {
         "metric": "ms/frame & Mpix/s for reproject+sample+EM at 1080p 1spp; % of HBM roofline",
@@ -238,12 +257,13 @@ def main():
         "config": {
             "workload": f"{W}x{H} spp{S}, {frames}-frame camera-pan sequence "
                         f"(timed frames {a.warmup}..{frames - 1}), Gamma {a.gamma_dtype}, "
-                        f"{'unfused' if a.unfused else 'fused reproject+sample'}",
-            "width": W, "height": H, "spp": S, "gamma_storage": a.gamma_dtype,
+                        f"{'unfused' if a.unfused else 'fused reproject+sample'}"
+                        + (f", {K} Gaussian lobes per pixel" if K > 1 else ""),
+            "width": W, "height": H, "spp": S, "gamma_storage": a.gamma_dtype, "lobes": K,
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_em" if dominant == "em" else "k_reproject_sample",
+            "kernel": dom_name,
             "achieved": round(dom_gbs, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -370,10 +390,10 @@ def bench_batched(a):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(seed, spp, W, H, budget_s):
+def cpu_baseline(seed, spp, W, H, budget_s, lobes=1):
     """The FP64 oracle's reproject + sample + EM on the host cores (light field
     excluded like on the GPU): whole frames of the same sequence from frame 0
-    until the time budget is spent."""
+    until the time budget is spent (the K-lobe functions when lobes > 1)."""
     import oracle as O
     from paper_2112_09728_amd import workload as wl
 
@@ -388,13 +408,17 @@ def cpu_baseline(seed, spp, W, H, budget_s):
         v = O.OView(fr, fr["motion"], fr["disocc"])
         P = O.params(seed, frame=n)
         t0 = time.time()
-        g1, _ = O.reproject(P, v, v_prev if v_prev is not None else v, gamma)
-        rec = O.sample(P, v, g1, spp)
+        if lobes == 1:
+            g1, _ = O.reproject(P, v, v_prev if v_prev is not None else v, gamma)
+            rec = O.sample(P, v, g1, spp)
+        else:
+            g1, _ = O.reproject_k(P, lobes, v, v_prev if v_prev is not None else v, gamma)
+            rec = O.sample_k(P, lobes, v, g1, spp)
         t1 = time.time()
         rec["radiance"] = O.light(fr["lights"], float(fr["ambient"]), fr["vis"], rec["dir"],
                                   rec["strategy"])
         t2 = time.time()
-        gamma = O.em(P, v, rec, g1)
+        gamma = O.em(P, v, rec, g1) if lobes == 1 else O.em_k(P, lobes, v, rec, g1)
         t3 = time.time()
         spent += (t1 - t0) + (t3 - t2)
         v_prev = v
@@ -408,7 +432,8 @@ def cpu_baseline(seed, spp, W, H, budget_s):
         "ms_per_frame": round(ms, 1),
         "cores": O.num_threads(),
         "kind": "oracle",
-        "sample": f"frames 0..{n - 1} of the same {W}x{H} spp{spp} pan sequence, whole frames "
+        "sample": f"frames 0..{n - 1} of the same {W}x{H} spp{spp} pan sequence"
+                  + (f" at {lobes} lobes" if lobes > 1 else "") + ", whole frames "
                   f"({time.time() - t_all:.0f} s wall incl. the untimed light field)",
     }
 

@@ -15,9 +15,9 @@
 //
 // Kernels: one lane per pixel.  The streaming pass (reprojection + sampling)
 // and the densities use the 64x4 XCD-banded tiles of the single-lobe path;
-// the training pass stages a tile's records with its 3-pixel halo in LDS
-// (the same staging and pick decoding as the single-lobe pass) and runs the
-// E-step of each pixel in its own lane, in natural order.
+// the training pass uses the single-lobe pass's LDS staging of a tile's
+// records, its compacted training lists and its lane balancing, with the
+// E-step and merge of K lobes.
 #pragma once
 #include "pg_kernels.hpp"
 
@@ -312,31 +312,60 @@ __device__ __forceinline__ void lobes_visit(const LobesCtx<K> &c, float4 r, floa
   }
 }
 
-// Training pass with K lobes (Sec. 3.2, Sec. 4.2): the records of a TW x TH
-// tile and its halo staged in LDS, then each pixel's training set (own
-// samples, then N(k) picks of stream 1) visited from LDS in the order of the
-// oracle, and the stepwise merge of every lobe.
-// Dynamic LDS: records [spp][SH][SW] float4.
+// Training pass with K lobes (Sec. 3.2, Sec. 4.2), on the tile machinery of
+// the single-lobe pass: the records of a TW x TH tile and its halo staged in
+// LDS, the pixels sorted by candidate count to build their training lists
+// (own samples, then the N(k) picks of stream 1, rejected candidates
+// compacted away), sorted again by list length so that the lanes of a wave
+// carry nearly equal work, then the E-step of each lane's pixel over its list
+// and the stepwise merge of every lobe.
+// Dynamic LDS: records [spp][SH][SW] float4, then lists [spp + 20][NT] uint16.
 template <int K, int TW, int TH>
 __global__ __launch_bounds__(TW *TH) void k_lobes_em(ParamsK P, ViewK v, SamplesK S, float *__restrict__ gamma,
                                                      int tiles_x, int n_tiles) {
-  constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH;
+  constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH, NT = TW * TH;
   extern __shared__ float4 lds[];
+  __shared__ EmShared<NT> sh;
   const int tile = xcd_tile(blockIdx.x, n_tiles);
   const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
-  stage_records<TW, TH>(v, S, lds, tx0, ty0, 0);
-  __syncthreads();
-  const int lx = (int)threadIdx.x % TW, ly = (int)threadIdx.x / TW;
-  const int x = tx0 + lx, y = ty0 + ly;
-  if (x >= v.W || y >= v.H) return;  // no barrier follows
+  const int t = threadIdx.x;
+  const int spp = S.spp;
   const int plane = v.H * v.pitch;
-  const int idx = y * v.pitch + x;
-  const PixelIn pin = load_pixel(v, idx);
-  if (!(dot3(pin.n, pin.o) > 0.0f && pin.rough >= P.rough_min)) return;
+  uint16_t *list = reinterpret_cast<uint16_t *>(lds + spp * SA);
+  if (t < 2 * kMaxLen) (&sh.cnt[0][0])[t] = 0;
+  // the candidate count of this lane's pixel (0 when it is not trained)
+  int ncand = 0;
+  {
+    const int x0 = tx0 + t % TW, y0 = ty0 + t / TW;
+    if (x0 < v.W && y0 < v.H) {
+      const int idx0 = y0 * v.pitch + x0;
+      const PixelIn pin = load_pixel(v, idx0);
+      if (dot3(pin.n, pin.o) > 0.0f && pin.rough >= P.rough_min)
+        ncand = spp + n_picks(P, (int)gamma[(6 * K + 1) * plane + idx0]);
+    }
+  }
+  stage_records<TW, TH>(v, S, lds, tx0, ty0, 0);
+  sh.work[t] = (uint8_t)ncand;
+  __syncthreads();
+  int me;
+  {
+    const int pa = balance<NT>(ncand, t, sh.cnt[0], sh.perm, (int)blockIdx.x);
+    const int nc = sh.work[pa];
+    int len = 0;
+    if (nc > 0) {
+      const int lx = pa % TW, ly = pa / TW;
+      len = build_list<TW, TH>(P, lds, list, pa, lx, ly, nc - spp, spp, (uint32_t)((ty0 + ly) * v.W + tx0 + lx));
+    }
+    sh.work[pa] = (uint8_t)len;
+    me = balance<NT>(len, pa, sh.cnt[1], sh.perm, (int)blockIdx.x + 1);
+  }
+  const int len = sh.work[me];
+  if (len == 0) return;  // no barrier follows
+  const int idx = (ty0 + me / TW) * v.pitch + tx0 + me % TW;
   float g[6 * K + 2];
   lobes_load<K>(gamma, plane, idx, g);
   LobesCtx<K> c;
-  c.px = make_pixel(P, pin.n, pin.o, pin.rough, v.alb[idx]);
+  c.px = make_pixel(P, load3(v.n, plane, idx), load3(v.o, plane, idx), v.rough[idx], v.alb[idx]);
   float tot = 0.0f;
 #pragma unroll
   for (int j = 0; j < K; ++j) {
@@ -349,22 +378,7 @@ __global__ __launch_bounds__(TW *TH) void k_lobes_em(ParamsK P, ViewK v, Samples
   Accum a[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) a[j] = Accum{0, 0, 0, 0, 0, 0, 0};
-  const int spp = S.spp;
-  const int own = (ly + kR) * SW + (lx + kR);
-  for (int s = 0; s < spp; ++s) lobes_visit<K>(c, lds[s * SA + own], B0, a);
-  const int npick = n_picks(P, (int)g[6 * K + 1]);
-  const uint32_t cs = (uint32_t)(kCand * spp);
-  const uint32_t inv_spp = (65536u + (uint32_t)spp - 1u) / (uint32_t)spp;
-  const uint32_t pix = (uint32_t)(y * v.W + x);
-  for (int m0 = 0; m0 < npick; m0 += 8) {
-    const uint4 w4 = philox4x32_10(pix, P.frame, (1u << 16) | (uint32_t)(m0 >> 3), P.view, P.key0, P.key1);
-    float4 r[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) r[j] = lds[pick_entry<SA, SW>(w4, j, cs, inv_spp, (uint32_t)spp, own)];
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-      if (m0 + j < npick) lobes_visit<K>(c, r[j], B0, a);
-  }
+  for (int j = 0; j < len; ++j) lobes_visit<K>(c, lds[list[j * NT + me]], B0, a);
   if (!(B0 > 0.0f)) return;  // no training sample: the model stays as it is
   const float Wv = g[6 * K], kk = g[6 * K + 1];
   const float eta = frcp(kk + 1.0f);
@@ -391,13 +405,13 @@ __global__ __launch_bounds__(TW *TH) void k_lobes_em(ParamsK P, ViewK v, Samples
   }
   if (!(P.flags & kNoClamp)) {
     const float fl = P.pi_lo * (0.25f / (float)K);
-    float t = 0.0f;
+    float tt = 0.0f;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
       pn[j] = fmaxf(pn[j], fl);
-      t += pn[j];
+      tt += pn[j];
     }
-    const float scale = t > 0.0f ? fminf(fmaxf(t, P.pi_lo), P.pi_hi) / t : 0.0f;
+    const float scale = tt > 0.0f ? fminf(fmaxf(tt, P.pi_lo), P.pi_hi) / tt : 0.0f;
 #pragma unroll
     for (int j = 0; j < K; ++j) pn[j] *= scale;
   }

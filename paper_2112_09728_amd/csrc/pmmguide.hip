@@ -597,11 +597,12 @@ pg_status pg_em_update_lobes(const pg_params *p, int32_t lobes, const pg_view *v
   const ViewK V = to_k(v);
   const SamplesK S = to_k(in);
   hipStream_t s = (hipStream_t)stream;
-  // 32x8 tiles, 32x4 above 4 spp (the records of 8 planes and the halo fit
-  // 64 KiB)
+  // 32x8 tiles, 32x4 above 4 spp (the records of 8 planes with the halo and
+  // the lists fit 64 KiB)
   const int TH = in->spp > 4 ? 4 : 8;
   const int tx = (V.W + 31) / 32, ty = (V.H + TH - 1) / TH;
-  const size_t lds = (size_t)in->spp * (32 + 2 * kR) * (TH + 2 * kR) * sizeof(float4);
+  const size_t lds = (size_t)in->spp * (32 + 2 * kR) * (TH + 2 * kR) * sizeof(float4) +
+                     (size_t)(in->spp + 20) * 32 * TH * sizeof(uint16_t);
   return dispatch_lobes(lobes, [&](auto kc) {
     constexpr int K = decltype(kc)::value;
     if (TH == 8)
