@@ -312,6 +312,70 @@ __device__ __forceinline__ void lobes_visit(const LobesCtx<K> &c, float4 r, floa
   }
 }
 
+// E-step of one pixel over its training list (LDS indices list[j * stride])
+// and the stepwise merge of every lobe, in place on g.  A list whose samples
+// carry no weight leaves g as it is.
+template <int K>
+__device__ __forceinline__ void lobes_update(const ParamsK &P, const ViewK &v, int idx, const float4 *lds,
+                                             const uint16_t *list, int stride, int len, float g[6 * K + 2]) {
+  const int plane = v.H * v.pitch;
+  LobesCtx<K> c;
+  c.px = make_pixel(P, load3(v.n, plane, idx), load3(v.o, plane, idx), v.rough[idx], v.alb[idx]);
+  float tot = 0.0f;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    c.G[j] = gauss_setup(g[6 * j], g[6 * j + 1], g[6 * j + 2], g[6 * j + 3], g[6 * j + 4], P.eps);
+    c.pi[j] = g[6 * j + 5];
+    tot += c.pi[j];
+  }
+  c.one_m_tot = 1.0f - tot;
+  float B0 = 0.0f;
+  Accum a[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) a[j] = Accum{0, 0, 0, 0, 0, 0, 0};
+  for (int j = 0; j < len; ++j) lobes_visit<K>(c, lds[list[j * stride]], B0, a);
+  if (!(B0 > 0.0f)) return;
+  const float Wv = g[6 * K], kk = g[6 * K + 1];
+  const float eta = frcp(kk + 1.0f);
+  const float sw = fmaf(1.0f - eta, Wv, eta * B0);
+  const float isw = 1.0f / sw;
+  float pn[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    float *l = g + 6 * j;
+    const float so = (1.0f - eta) * l[5] * Wv;
+    const float sn = eta * a[j].B1;
+    const float sg = so + sn;
+    if (sg > 0.0f && a[j].B1 > 0.0f) {
+      const float al = so / sg, be = sn / sg;
+      const float dx = l[0] - a[j].mx, dy = l[1] - a[j].my;
+      const float ab = al * be;
+      l[0] = fmaf(al, l[0], be * a[j].mx);
+      l[1] = fmaf(al, l[1], be * a[j].my);
+      l[2] = fmaf(ab * dx, dx, fmaf(al, l[2], be * a[j].sxx));
+      l[3] = fmaf(ab * dx, dy, fmaf(al, l[3], be * a[j].sxy));
+      l[4] = fmaf(ab * dy, dy, fmaf(al, l[4], be * a[j].syy));
+    }
+    pn[j] = sg * isw;
+  }
+  if (!(P.flags & kNoClamp)) {
+    const float fl = P.pi_lo * (0.25f / (float)K);
+    float tt = 0.0f;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      pn[j] = fmaxf(pn[j], fl);
+      tt += pn[j];
+    }
+    const float scale = tt > 0.0f ? fminf(fmaxf(tt, P.pi_lo), P.pi_hi) / tt : 0.0f;
+#pragma unroll
+    for (int j = 0; j < K; ++j) pn[j] *= scale;
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) g[6 * j + 5] = pn[j];
+  g[6 * K] = sw;
+  g[6 * K + 1] = fminf(kk + 1.0f, (float)P.k_max);
+}
+
 // Training pass with K lobes (Sec. 3.2, Sec. 4.2), on the tile machinery of
 // the single-lobe pass: the records of a TW x TH tile and its halo staged in
 // LDS, the pixels sorted by candidate count to build their training lists
@@ -319,7 +383,8 @@ __device__ __forceinline__ void lobes_visit(const LobesCtx<K> &c, float4 r, floa
 // compacted away), sorted again by list length so that the lanes of a wave
 // carry nearly equal work, then the E-step of each lane's pixel over its list
 // and the stepwise merge of every lobe.
-// Dynamic LDS: records [spp][SH][SW] float4, then lists [spp + 20][NT] uint16.
+// Dynamic LDS: records [spp][SH][SW] float4, then lists [spp + 20][NT]
+// uint16; the write-back reuses it ([6K + 2][NT] float).
 template <int K, int TW, int TH>
 __global__ __launch_bounds__(TW *TH) void k_lobes_em(ParamsK P, ViewK v, SamplesK S, float *__restrict__ gamma,
                                                      int tiles_x, int n_tiles) {
@@ -360,66 +425,27 @@ __global__ __launch_bounds__(TW *TH) void k_lobes_em(ParamsK P, ViewK v, Samples
     me = balance<NT>(len, pa, sh.cnt[1], sh.perm, (int)blockIdx.x + 1);
   }
   const int len = sh.work[me];
-  if (len == 0) return;  // no barrier follows
-  const int idx = (ty0 + me / TW) * v.pitch + tx0 + me % TW;
   float g[6 * K + 2];
-  lobes_load<K>(gamma, plane, idx, g);
-  LobesCtx<K> c;
-  c.px = make_pixel(P, load3(v.n, plane, idx), load3(v.o, plane, idx), v.rough[idx], v.alb[idx]);
-  float tot = 0.0f;
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    c.G[j] = gauss_setup(g[6 * j], g[6 * j + 1], g[6 * j + 2], g[6 * j + 3], g[6 * j + 4], P.eps);
-    c.pi[j] = g[6 * j + 5];
-    tot += c.pi[j];
+  if (len > 0) {  // otherwise no training sample (or no pixel): the model stays as it is
+    const int idx = (ty0 + me / TW) * v.pitch + tx0 + me % TW;
+    lobes_load<K>(gamma, plane, idx, g);
+    lobes_update<K>(P, v, idx, lds, list + me, NT, len, g);
   }
-  c.one_m_tot = 1.0f - tot;
-  float B0 = 0.0f;
-  Accum a[K];
+  // write-back in natural order through LDS (full cache lines), over the
+  // records and lists once no lane reads them
+  float *wb = reinterpret_cast<float *>(lds);
+  __syncthreads();
+  if (len > 0) {
 #pragma unroll
-  for (int j = 0; j < K; ++j) a[j] = Accum{0, 0, 0, 0, 0, 0, 0};
-  for (int j = 0; j < len; ++j) lobes_visit<K>(c, lds[list[j * NT + me]], B0, a);
-  if (!(B0 > 0.0f)) return;  // no training sample: the model stays as it is
-  const float Wv = g[6 * K], kk = g[6 * K + 1];
-  const float eta = frcp(kk + 1.0f);
-  const float sw = fmaf(1.0f - eta, Wv, eta * B0);
-  const float isw = 1.0f / sw;
-  float pn[K];
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    float *l = g + 6 * j;
-    const float so = (1.0f - eta) * l[5] * Wv;
-    const float sn = eta * a[j].B1;
-    const float sg = so + sn;
-    if (sg > 0.0f && a[j].B1 > 0.0f) {
-      const float al = so / sg, be = sn / sg;
-      const float dx = l[0] - a[j].mx, dy = l[1] - a[j].my;
-      const float ab = al * be;
-      l[0] = fmaf(al, l[0], be * a[j].mx);
-      l[1] = fmaf(al, l[1], be * a[j].my);
-      l[2] = fmaf(ab * dx, dx, fmaf(al, l[2], be * a[j].sxx));
-      l[3] = fmaf(ab * dx, dy, fmaf(al, l[3], be * a[j].sxy));
-      l[4] = fmaf(ab * dy, dy, fmaf(al, l[4], be * a[j].syy));
-    }
-    pn[j] = sg * isw;
+    for (int c = 0; c < 6 * K + 2; ++c) wb[c * NT + me] = g[c];
   }
-  if (!(P.flags & kNoClamp)) {
-    const float fl = P.pi_lo * (0.25f / (float)K);
-    float tt = 0.0f;
+  __syncthreads();
+  const int x0 = tx0 + t % TW, y0 = ty0 + t / TW;
+  if (sh.work[t] > 0 && x0 < v.W && y0 < v.H) {
+    const int idx0 = y0 * v.pitch + x0;
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-      pn[j] = fmaxf(pn[j], fl);
-      tt += pn[j];
-    }
-    const float scale = tt > 0.0f ? fminf(fmaxf(tt, P.pi_lo), P.pi_hi) / tt : 0.0f;
-#pragma unroll
-    for (int j = 0; j < K; ++j) pn[j] *= scale;
+    for (int c = 0; c < 6 * K + 2; ++c) gamma[c * plane + idx0] = wb[c * NT + t];
   }
-#pragma unroll
-  for (int j = 0; j < K; ++j) g[6 * j + 5] = pn[j];
-  g[6 * K] = sw;
-  g[6 * K + 1] = fminf(kk + 1.0f, (float)P.k_max);
-  lobes_store<K>(gamma, plane, idx, g);
 }
 
 }  // namespace pgk

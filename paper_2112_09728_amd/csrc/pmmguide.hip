@@ -601,8 +601,10 @@ pg_status pg_em_update_lobes(const pg_params *p, int32_t lobes, const pg_view *v
   // the lists fit 64 KiB)
   const int TH = in->spp > 4 ? 4 : 8;
   const int tx = (V.W + 31) / 32, ty = (V.H + TH - 1) / TH;
-  const size_t lds = (size_t)in->spp * (32 + 2 * kR) * (TH + 2 * kR) * sizeof(float4) +
-                     (size_t)(in->spp + 20) * 32 * TH * sizeof(uint16_t);
+  const size_t lds_tile = (size_t)in->spp * (32 + 2 * kR) * (TH + 2 * kR) * sizeof(float4) +
+                          (size_t)(in->spp + 20) * 32 * TH * sizeof(uint16_t);
+  const size_t lds_wb = (size_t)(6 * lobes + 2) * 32 * TH * sizeof(float);  // write-back area
+  const size_t lds = lds_tile > lds_wb ? lds_tile : lds_wb;
   return dispatch_lobes(lobes, [&](auto kc) {
     constexpr int K = decltype(kc)::value;
     if (TH == 8)
