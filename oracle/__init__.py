@@ -38,6 +38,20 @@ class Params(C.Structure):
     ]
 
 
+class Ceiling(C.Structure):
+    _fields_ = [("z", C.c_double), ("period", C.c_double), ("x0", C.c_double), ("y0", C.c_double),
+                ("ambient", C.c_double), ("nx", C.c_int32), ("ny", C.c_int32), ("lamps", C.c_void_p)]
+
+
+def ceiling(c):
+    """Ceiling struct from the workload's dict (the lamp table is kept alive on the struct)."""
+    lamps = _f32(c["lamps"])
+    C_ = Ceiling(float(c["z"]), float(c["period"]), float(c["x0"]), float(c["y0"]), float(c["ambient"]),
+                 lamps.shape[1], lamps.shape[0], _ptr(lamps))
+    C_._keep = lamps
+    return C_
+
+
 class Rect(C.Structure):
     _fields_ = [("x0", C.c_int32), ("y0", C.c_int32), ("x1", C.c_int32), ("y1", C.c_int32)]
 
@@ -90,6 +104,9 @@ def _declare(L):
     L.orc_sample_k.argtypes = [P, i32, P, P, i32, P, P, P, P, P, Rect]
     L.orc_pdf_k.argtypes = [P, i32, P, P, i32, P, P, Rect]
     L.orc_em_k.argtypes = [P, i32, P, i32, P, P, P, P, P, P, Rect]
+    L.orc_em_vpl.argtypes = [P, i32, P, P, i32, P, P, P, P, P, P, P, Rect]
+    L.orc_light_ceiling.argtypes = [P, P, P, i32, P, P, P, P, Rect]
+    L.orc_reference_ceiling.argtypes = [P, P, P, P, i32, P, i64, P, P]
     L.orc_num_threads.restype = i32
 
 
@@ -410,6 +427,51 @@ def em_k(P, K, view, rec, gamma, rect=None, with_stats=False):
     lib().orc_em_k(C.byref(P), K, C.byref(view.c), spp, _ptr(d), _ptr(pb), _ptr(st), _ptr(L), _ptr(g),
                    _ptr(stats), _rect(view, rect))
     return (g, stats) if with_stats else g
+
+
+# --- positional reuse of virtual point lights and the ceiling workload --------
+
+def em_vpl(P, K, view, position, rec, gamma, rect=None, with_stats=False):
+    """The K-lobe update with training directions re-derived from each
+    sample's virtual point light (rec["hit_dist"] [spp][H][W])."""
+    g = _f64(gamma).copy()
+    assert g.shape[0] == 6 * K + 2
+    pos = _f32(position)
+    spp = rec["strategy"].shape[0]
+    d, pb, L, t = _f64(rec["dir"]), _f64(rec["pdf_brdf"]), _f64(rec["radiance"]), _f64(rec["hit_dist"])
+    st = np.ascontiguousarray(rec["strategy"], dtype=np.uint8)
+    stats = np.zeros((K + 1,) + g.shape[1:]) if with_stats else None
+    lib().orc_em_vpl(C.byref(P), K, C.byref(view.c), _ptr(pos), spp, _ptr(d), _ptr(pb), _ptr(st), _ptr(L),
+                     _ptr(t), _ptr(g), _ptr(stats), _rect(view, rect))
+    return (g, stats) if with_stats else g
+
+
+def light_ceiling(ceil, view, position, dirs, strategy, rect=None):
+    """(radiance, hit distance) [spp][H][W] of the ceiling stand-in."""
+    Cc = ceiling(ceil) if isinstance(ceil, dict) else ceil
+    pos = _f32(position)
+    dirs = _f64(dirs)
+    strategy = np.ascontiguousarray(strategy, dtype=np.uint8)
+    spp = strategy.shape[0]
+    L = np.zeros(strategy.shape)
+    t = np.zeros(strategy.shape)
+    lib().orc_light_ceiling(C.byref(Cc), C.byref(view.c), _ptr(pos), spp, _ptr(dirs), _ptr(strategy), _ptr(L),
+                            _ptr(t), _rect(view, rect))
+    return L, t
+
+
+def reference_ceiling(P, view, position, ceil, pixels, n_samples=16384):
+    """Reference int f_r E cos under the ceiling for flat pixel indices:
+    (mean, standard error), BRDF sampling with n_samples <= 65536 draws."""
+    assert 0 < n_samples <= 65536
+    Cc = ceiling(ceil) if isinstance(ceil, dict) else ceil
+    pos = _f32(position)
+    idx = np.ascontiguousarray(pixels, dtype=np.int64)
+    mean = np.zeros(idx.shape[0])
+    se = np.zeros(idx.shape[0])
+    lib().orc_reference_ceiling(C.byref(P), C.byref(view.c), _ptr(pos), C.byref(Cc), idx.shape[0], _ptr(idx),
+                                int(n_samples), _ptr(mean), _ptr(se))
+    return mean, se
 
 
 def num_threads():

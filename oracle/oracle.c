@@ -790,6 +790,7 @@ typedef struct tset_t {
   int n;
   double dir[MAX_SET][3];
   double L[MAX_SET], psrc[MAX_SET];
+  int64_t pix[MAX_SET], rec[MAX_SET]; /* source pixel (plane index) and record offset */
 } tset_t;
 
 static void gather_set(const orc_params *P, const orc_view *v, int32_t spp, const double *dir,
@@ -809,6 +810,8 @@ static void gather_set(const orc_params *P, const orc_view *v, int32_t spp, cons
     T->dir[T->n][2] = dir[2 * spl + o];
     T->L[T->n] = radiance[o];
     T->psrc[T->n] = pdf_brdf[o];
+    T->pix[T->n] = (int64_t)qy * v->pitch + qx;
+    T->rec[T->n] = o;
     T->n++;
   }
   (void)H;
@@ -1368,9 +1371,13 @@ void orc_pdf_k(const orc_params *P, int32_t K, const orc_view *v, const double *
  * under the model's weights, per-lobe batch statistics (B1_j, mean, scatter
  * under the weights w gam_j), and the stepwise merge of each lobe with its
  * evidence; then the weight clamp of the extension's reading. */
-void orc_em_k(const orc_params *P, int32_t K, const orc_view *v, int32_t spp, const double *dir,
-              const double *pdf_brdf, const uint8_t *strategy, const double *radiance, double *gamma,
-              double *stats, orc_rect r) {
+/* The K-lobe update; with positions and hit distances (both non-NULL) every
+ * training sample's direction is re-derived from its virtual point light:
+ * y = x_q + t w_q, w = (y - x_p)/|y - x_p|, and w_q itself where t is not
+ * finite (the sample left the scene; its light is at infinity). */
+static void em_k_impl(const orc_params *P, int32_t K, const orc_view *v, int32_t spp, const double *dir,
+                      const double *pdf_brdf, const uint8_t *strategy, const double *radiance,
+                      const float *position, const double *hit_dist, double *gamma, double *stats, orc_rect r) {
   const int NC = nch_k(K);
   const int64_t pl = (int64_t)v->height * v->pitch;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -1386,6 +1393,17 @@ void orc_em_k(const orc_params *P, int32_t K, const orc_view *v, int32_t spp, co
       for (int c = 0; c < NC; ++c) g[c] = gamma[c * pl + idx];
       const double kk = g[6 * K + 1], Wv = g[6 * K];
       gather_set(P, v, spp, dir, pdf_brdf, strategy, radiance, x, y, (int)kk, T);
+      if (position && hit_dist) {
+        const double xp[3] = {position[idx], position[pl + idx], position[2 * pl + idx]};
+        for (int j = 0; j < T->n; ++j) {
+          const double t = hit_dist[T->rec[j]];
+          if (!isfinite(t)) continue;
+          const int64_t q = T->pix[j];
+          double wq[3] = {T->dir[j][0], T->dir[j][1], T->dir[j][2]};
+          normalize3(wq);
+          for (int c = 0; c < 3; ++c) T->dir[j][c] = (double)position[c * pl + q] + t * wq[c] - xp[c];
+        }
+      }
       gauss_t G[MAXK];
       for (int j = 0; j < K; ++j) G[j] = gauss_setup(g + 6 * j, (double)P->eps_sigma);
       const double tot = total_pi_k(g, K);
@@ -1452,6 +1470,123 @@ void orc_em_k(const orc_params *P, int32_t K, const orc_view *v, int32_t spp, co
       for (int c = 0; c < NC; ++c) gamma[c * pl + idx] = g[c];
     }
     free(T);
+  }
+}
+
+void orc_em_k(const orc_params *P, int32_t K, const orc_view *v, int32_t spp, const double *dir,
+              const double *pdf_brdf, const uint8_t *strategy, const double *radiance, double *gamma,
+              double *stats, orc_rect r) {
+  em_k_impl(P, K, v, spp, dir, pdf_brdf, strategy, radiance, NULL, NULL, gamma, stats, r);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Positional reuse of virtual point lights (Fig. 2 caption, Sec. 3.1): the
+ * trace stores with each sample the position y of its next surface
+ * interaction, and a neighbour's sample trains pixel p along the direction
+ * from x_p to that y, with the neighbour's radiance and source density (the
+ * paper reuses the VPL as it is; no change-of-measure factor).  Positions
+ * [3][H*pitch] are the pixels' world positions; hit_dist [spp][H*pitch] the
+ * distance t to y along the sample's direction (+inf: no interaction). */
+void orc_em_vpl(const orc_params *P, int32_t K, const orc_view *v, const float *position, int32_t spp,
+                const double *dir, const double *pdf_brdf, const uint8_t *strategy, const double *radiance,
+                const double *hit_dist, double *gamma, double *stats, orc_rect r) {
+  em_k_impl(P, K, v, spp, dir, pdf_brdf, strategy, radiance, position, hit_dist, gamma, stats, r);
+}
+
+/* Near-field stand-in for the trace (the workload of the positional reuse):
+ * an emitting plane z = z_c above the surface, its emission a lattice of
+ * Gaussian spots, lamp (i, j) at (sx, sy) with radius r and intensity c:
+ *   E(y) = ambient + sum over the 3x3 lattice cells around y's cell of
+ *          c exp(-|y_xy - s|^2 / (2 r^2)),
+ * cell (i, j) = floor((y - origin) / period).  A live sample at x with world
+ * direction w (normalised) hits the plane at t = (z_c - x_z) / w_z when
+ * w_z > 0 (L = E(x + t w)); otherwise it leaves the scene (t = +inf, L =
+ * ambient).  Null samples get L = 0 and t = 0. */
+static double ceiling_emission(const orc_ceiling *C, double yx, double yy) {
+  const int ci = (int)floor((yx - C->x0) / C->period), cj = (int)floor((yy - C->y0) / C->period);
+  double E = C->ambient;
+  for (int dj = -1; dj <= 1; ++dj)
+    for (int di = -1; di <= 1; ++di) {
+      const int i = ci + di, j = cj + dj;
+      if (i < 0 || j < 0 || i >= C->nx || j >= C->ny) continue;
+      const float *l = C->lamps + 4 * ((int64_t)j * C->nx + i);
+      const double dx = yx - l[0], dy = yy - l[1], rr = (double)l[2] * l[2];
+      E += (double)l[3] * exp(-(dx * dx + dy * dy) / (2.0 * rr));
+    }
+  return E;
+}
+
+void orc_light_ceiling(const orc_ceiling *C, const orc_view *v, const float *position, int32_t spp,
+                       const double *dir, const uint8_t *strategy, double *radiance, double *hit_dist,
+                       orc_rect r) {
+  const int64_t pl = (int64_t)v->height * v->pitch;
+  const int64_t spl = (int64_t)spp * pl;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int y = r.y0; y < r.y1; ++y) {
+    for (int x = r.x0; x < r.x1; ++x) {
+      const int64_t idx = (int64_t)y * v->pitch + x;
+      const double xp[3] = {position[idx], position[pl + idx], position[2 * pl + idx]};
+      for (int s = 0; s < spp; ++s) {
+        const int64_t o = (int64_t)s * pl + idx;
+        double L = 0.0, t = 0.0;
+        if (strategy[o] == 1 || strategy[o] == 2) {
+          double w[3] = {dir[o], dir[spl + o], dir[2 * spl + o]};
+          normalize3(w);
+          if (w[2] > 0.0) {
+            t = (C->z - xp[2]) / w[2];
+            L = ceiling_emission(C, xp[0] + t * w[0], xp[1] + t * w[1]);
+          } else {
+            t = INFINITY;
+            L = C->ambient;
+          }
+        }
+        radiance[o] = L;
+        hit_dist[o] = t;
+      }
+    }
+  }
+}
+
+/* Reference value of int f_r E(y(w)) cos dw for a list of pixels under the
+ * ceiling: Monte Carlo in FP64 with n BRDF-sampling draws per pixel (Philox
+ * counter (pixel, frame, 7 * 2^16 + sample, view)); null draws count zero.
+ * Returns the mean and its standard error. */
+void orc_reference_ceiling(const orc_params *P, const orc_view *v, const float *position, const orc_ceiling *C,
+                           int32_t n_pixels, const int64_t *pixels, int64_t n, double *mean, double *stderr_out) {
+  const int64_t pl = (int64_t)v->height * v->pitch;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t i = 0; i < n_pixels; ++i) {
+    const int64_t pix = pixels[i];
+    const int x = (int)(pix % v->width), y = (int)(pix / v->width);
+    const int64_t idx = (int64_t)y * v->pitch + x;
+    const pixel_t px = load_pixel(P, v, idx);
+    const double xp[3] = {position[idx], position[pl + idx], position[2 * pl + idx]};
+    double s1 = 0.0, s2 = 0.0;
+    if (px.valid) {
+      for (int64_t k = 0; k < n; ++k) {
+        uint32_t w4[4];
+        rng_words(P, (uint32_t)pix, 7, (uint32_t)k, w4);
+        double l[3], m2;
+        if (!brdf_sample(px.wo, px.alpha, (double)P->s_diffuse, uniform24(w4[1]), uniform24(w4[2]),
+                         uniform24(w4[3]), l, &m2))
+          continue;
+        const double pb = brdf_pdf(px.wo, l, px.alpha, (double)P->s_diffuse);
+        if (!(pb > 0.0)) continue;
+        double w[3];
+        to_world(&px.f, l, w);
+        double E = C->ambient;
+        if (w[2] > 0.0) {
+          const double t = (C->z - xp[2]) / w[2];
+          E = ceiling_emission(C, xp[0] + t * w[0], xp[1] + t * w[1]);
+        }
+        const double f = brdf_f(px.wo, l, px.alpha, px.albedo, (double)P->f0) * E * l[2] / pb;
+        s1 += f;
+        s2 += f * f;
+      }
+    }
+    const double m = s1 / (double)n;
+    mean[i] = m;
+    stderr_out[i] = sqrt(fmax(s2 / (double)n - m * m, 0.0) / (double)n);
   }
 }
 

@@ -147,6 +147,20 @@ void orc_pdf_k(const orc_params *P, int32_t K, const orc_view *v, const double *
 void orc_em_k(const orc_params *P, int32_t K, const orc_view *v, int32_t spp, const double *dir,
               const double *pdf_brdf, const uint8_t *strategy, const double *radiance, double *gamma,
               double *stats, orc_rect r);
+/* Positional reuse of virtual point lights and its near-field workload. */
+typedef struct orc_ceiling {
+  double z, period, x0, y0, ambient; /* plane height, lattice period and origin */
+  int32_t nx, ny;                    /* lattice cells                            */
+  const float *lamps;                /* [ny][nx][4]: sx, sy, r, c                */
+} orc_ceiling;
+void orc_em_vpl(const orc_params *P, int32_t K, const orc_view *v, const float *position, int32_t spp,
+                const double *dir, const double *pdf_brdf, const uint8_t *strategy, const double *radiance,
+                const double *hit_dist, double *gamma, double *stats, orc_rect r);
+void orc_light_ceiling(const orc_ceiling *C, const orc_view *v, const float *position, int32_t spp,
+                       const double *dir, const uint8_t *strategy, double *radiance, double *hit_dist,
+                       orc_rect r);
+void orc_reference_ceiling(const orc_params *P, const orc_view *v, const float *position, const orc_ceiling *C,
+                           int32_t n_pixels, const int64_t *pixels, int64_t n, double *mean, double *stderr_out);
 int32_t orc_num_threads(void);
 
 #ifdef __cplusplus

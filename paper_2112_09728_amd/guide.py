@@ -34,6 +34,7 @@ class DeviceFrame:
                          dev(fr["roughness"]), dev(fr["albedo"]), dev(fr.get("motion")),
                          dev(fr.get("disocc")))
         self.vis = dev(fr["vis"])
+        self.position = dev(fr.get("position"))
 
 
 class Guide:

@@ -18,7 +18,11 @@ traced radiance with seeded synthetic data of the same shape:
   pixel, and a 2% disocclusion mask (none at frame 0) marks pixels whose
   history is discarded.  ``make_motion`` instead draws independent motion
   per pixel over a static G-buffer, a harder case for the reprojection
-  gather used by the tests.
+  gather used by the tests;
+* for the positional reuse of virtual point lights, each texel's world
+  position (x + 1/2, y + 1/2, height) and a near-field emitter above the
+  surface (``make_ceiling``): the plane z = 32 with a jittered lattice of
+  Gaussian lamps (period 48 texels, radius U[3, 8], intensity U[2, 30]).
 
 This module holds no arithmetic of the method itself: it only draws inputs.
 Both the GPU path and the CPU oracle consume the arrays it returns.
@@ -32,7 +36,7 @@ N_LIGHTS = 3
 SEED_BASE = 211209728
 
 # stream ids of the generator (kept apart so that each input is independent)
-_S_HEIGHT, _S_MATERIAL, _S_LIGHTS, _S_VIS, _S_MOTION, _S_MASK = 2, 3, 4, 5, 6, 7
+_S_HEIGHT, _S_MATERIAL, _S_LIGHTS, _S_VIS, _S_MOTION, _S_MASK, _S_CEILING = 2, 3, 4, 5, 6, 7, 8
 
 
 def _rng(seed: int, stream: int, frame: int = 0) -> np.random.Generator:
@@ -98,6 +102,8 @@ def make_scene(width: int, height: int, seed: int, margin: int = 0) -> dict:
     n = np.stack([-gx, -gy, np.ones_like(gx)])
     n /= np.sqrt((n * n).sum(0, keepdims=True))
     depth = 1000.0 - h
+    wx, wy = np.meshgrid(np.arange(width) + 0.5, np.arange(height) + 0.5)
+    position = np.stack([wx, wy, h])
     xs = np.arange(sw) + 0.5
     ys = np.arange(sh) + 0.5
     cam_h = float(max(sw, sh))
@@ -128,7 +134,27 @@ def make_scene(width: int, height: int, seed: int, margin: int = 0) -> dict:
         roughness=roughness.astype(np.float32),
         albedo=albedo.astype(np.float32),
         lights=lights, ambient=np.float32(AMBIENT), vis=vis,
+        position=position.astype(np.float32),
+        ceiling=make_ceiling(width, height, seed),
     )
+
+
+def make_ceiling(width: int, height: int, seed: int, z: float = 32.0, period: float = 48.0) -> dict:
+    """Near-field emitter over a world of width x height texels: the plane at
+    height z, lamps on a lattice of the given period covering the world and
+    one cell beyond each edge, each lamp at a uniform position in the middle
+    half of its cell with radius U[3, 8] and intensity U[2, 30].  lamps
+    [ny][nx][4] float32 holds (sx, sy, r, c)."""
+    rng = _rng(seed, _S_CEILING)
+    x0 = y0 = -period
+    nx = int(np.ceil((width + 2 * period) / period))
+    ny = int(np.ceil((height + 2 * period) / period))
+    sx = x0 + (np.arange(nx)[None, :] + rng.uniform(0.25, 0.75, (ny, nx))) * period
+    sy = y0 + (np.arange(ny)[:, None] + rng.uniform(0.25, 0.75, (ny, nx))) * period
+    r = rng.uniform(3.0, 8.0, (ny, nx))
+    c = rng.uniform(2.0, 30.0, (ny, nx))
+    return dict(z=z, period=period, x0=x0, y0=y0, ambient=AMBIENT,
+                lamps=np.stack([sx, sy, r, c], -1).astype(np.float32))
 
 
 def make_motion(width: int, height: int, seed: int, frame: int, moving: bool = True,
@@ -167,7 +193,7 @@ class Sequence:
         iy = np.floor(np.arange(H) + 0.5 + oy).astype(np.int64) + M
         out = dict(self.world)
         out["width"], out["height"] = W, H
-        for key in ("normal",):
+        for key in ("normal", "position"):
             out[key] = np.ascontiguousarray(self.world[key][:, iy[:, None], ix[None, :]])
         for key in ("depth", "roughness", "albedo", "vis"):
             out[key] = np.ascontiguousarray(self.world[key][iy[:, None], ix[None, :]])
@@ -225,8 +251,9 @@ def batched_views(n_views: int, sizes, spp_range, seed: int):
 def crop_scene(scene: dict, x0: int, y0: int, x1: int, y1: int) -> dict:
     """A sub-rectangle of a scene as a scene of its own (same lights)."""
     out = dict(scene)
-    for key in ("normal", "view_dir"):
-        out[key] = np.ascontiguousarray(scene[key][:, y0:y1, x0:x1])
+    for key in ("normal", "view_dir", "position"):
+        if key in scene:
+            out[key] = np.ascontiguousarray(scene[key][:, y0:y1, x0:x1])
     for key in ("depth", "roughness", "albedo", "vis"):
         out[key] = np.ascontiguousarray(scene[key][y0:y1, x0:x1])
     out["width"], out["height"] = x1 - x0, y1 - y0
