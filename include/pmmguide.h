@@ -267,6 +267,42 @@ pg_status pg_em_update_lobes(const pg_params *p, int32_t lobes, const pg_view *v
 pg_status pg_pdf_lobes(const pg_params *p, int32_t lobes, const pg_view *v, const float *gamma,
                        int32_t n_per_px, const float *dir, float *pdf_mix, void *stream);
 
+/* ---- Positional reuse of virtual point lights -----------------------------
+ * The trace stores with each sample the position y of its next surface
+ * interaction (the VPL, Fig. 2 caption and Sec. 3.1); a neighbour's sample
+ * then trains pixel p along the direction from p's own position x_p to y
+ * rather than along the neighbour's direction, with the neighbour's radiance
+ * and source density as they are (the paper reuses the VPL without a
+ * change-of-measure factor).  y is given by the pixel positions and the hit
+ * distance t of each sample: y = x_q + t w_q; a sample with t = +inf (no
+ * interaction) trains along w_q. */
+
+/* pg_em_update_lobes with positional reuse (K = lobes, 1 <= K <=
+ * PG_MAX_LOBES; K = 1 is the single-lobe model, whose 8 planes are the FP32
+ * layout of pg_gamma).  position [3][H*pitch] FP32: world position of each
+ * pixel's surface point; hit_dist [spp][H*pitch] FP32 as written by
+ * pg_light_ceiling (only entries of strategy-1 samples are read).  With every
+ * hit distance +inf the result is that of pg_em_update_lobes. */
+pg_status pg_em_update_vpl(const pg_params *p, int32_t lobes, const pg_view *v, const float *position,
+                           const pg_samples *in, const float *hit_dist, float *gamma_inout, void *stream);
+
+/* Near-field stand-in for the trace (workload of the positional reuse): an
+ * emitting plane z = z above the surface whose emission is
+ *   E(y) = ambient + sum over the 3x3 lamp cells around y of
+ *          c exp(-|y_xy - s|^2 / (2 r^2)),
+ * cell (i, j) = floor((y - origin) / period), lamp (i, j) = lamps[j][i] =
+ * (sx, sy, r, c).  For each sample of strategy 1 or 2 with world direction w
+ * (normalised): if w_z > 0, t = (z - x_z) / w_z and L = E(x + t w); else
+ * t = +inf and L = ambient.  Other samples get L = 0 and t = 0.  Writes
+ * samples->radiance and hit_dist [spp][H*pitch]. */
+typedef struct pg_ceiling {
+  float z, period, x0, y0, ambient;
+  int32_t nx, ny;
+  const float *lamps; /* [ny][nx][4] FP32 device memory, 16-byte aligned */
+} pg_ceiling;
+pg_status pg_light_ceiling(const pg_ceiling *c, const pg_view *v, const float *position,
+                           const pg_samples *samples, float *hit_dist, void *stream);
+
 /* ---- Batched frame: many views in two persistent launches ----------------
  * One frame of n views of any size and spp (Sec. 3.1 and Sec. 3.2 for each
  * view, with the light-field stand-in between them) as an upload of a packed

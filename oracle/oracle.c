@@ -1503,8 +1503,11 @@ void orc_em_vpl(const orc_params *P, int32_t K, const orc_view *v, const float *
  * w_z > 0 (L = E(x + t w)); otherwise it leaves the scene (t = +inf, L =
  * ambient).  Null samples get L = 0 and t = 0. */
 static double ceiling_emission(const orc_ceiling *C, double yx, double yy) {
-  const int ci = (int)floor((yx - C->x0) / C->period), cj = (int)floor((yy - C->y0) / C->period);
+  const double fx = (yx - C->x0) / C->period, fy = (yy - C->y0) / C->period;
   double E = C->ambient;
+  /* no lamp lies within one cell of a point outside [-1, n + 1) */
+  if (!(fx >= -1.0 && fx < C->nx + 1.0 && fy >= -1.0 && fy < C->ny + 1.0)) return E;
+  const int ci = (int)floor(fx), cj = (int)floor(fy);
   for (int dj = -1; dj <= 1; ++dj)
     for (int di = -1; di <= 1; ++di) {
       const int i = ci + di, j = cj + dj;

@@ -58,6 +58,11 @@ class PgLights(C.Structure):
                 ("light", (C.c_float * 5) * MAX_LIGHTS)]
 
 
+class PgCeiling(C.Structure):
+    _fields_ = [("z", C.c_float), ("period", C.c_float), ("x0", C.c_float), ("y0", C.c_float),
+                ("ambient", C.c_float), ("nx", C.c_int32), ("ny", C.c_int32), ("lamps", C.c_void_p)]
+
+
 class PgBatchView(C.Structure):
     _fields_ = [("params", PgParams), ("cur", PgView), ("prev", PgView), ("gamma_in", PgGamma),
                 ("gamma_out", PgGamma), ("samples", PgSamples), ("vis", C.c_void_p),
@@ -67,7 +72,7 @@ class PgBatchView(C.Structure):
 EXPORTS = ("pg_params_default", "pg_reproject", "pg_sample_mis", "pg_reproject_sample", "pg_pdf",
            "pg_light_field", "pg_em_update", "pg_nll_backward", "pg_estimate", "pg_batch_table_bytes",
            "pg_batch_pack", "pg_frame_batched", "pg_reproject_sample_lobes", "pg_em_update_lobes",
-           "pg_pdf_lobes", "pg_philox", "pg_last_error")
+           "pg_pdf_lobes", "pg_em_update_vpl", "pg_light_ceiling", "pg_philox", "pg_last_error")
 MAX_LOBES = 4
 
 _lib = None
@@ -101,6 +106,8 @@ def lib():
         L.pg_reproject_sample_lobes.argtypes = [P, C.c_int32, P, P, P, P, P, P]
         L.pg_em_update_lobes.argtypes = [P, C.c_int32, P, P, P, P]
         L.pg_pdf_lobes.argtypes = [P, C.c_int32, P, P, C.c_int32, P, P, P]
+        L.pg_em_update_vpl.argtypes = [P, C.c_int32, P, P, P, P, P, P]
+        L.pg_light_ceiling.argtypes = [P, P, P, P, P, P]
         L.pg_philox.argtypes = [C.c_int32, P, C.c_uint64, P, P]
         L.pg_last_error.restype = C.c_char_p
         for name in EXPORTS[:-1]:
@@ -387,6 +394,48 @@ def pdf_lobes(p: PgParams, lobes: int, view: View, gamma, dirs):
     _check(lib().pg_pdf_lobes(C.byref(p), lobes, C.byref(view.c), _lobes_state(gamma, lobes, "gamma", view), n,
                               _ptr(dirs), _ptr(pmix), _stream()), "pg_pdf_lobes")
     return pmix
+
+
+# ------------------------------------ positional reuse of virtual point lights
+class Ceiling:
+    """Device copy of the near-field emitter (lamps [ny][nx][4] FP32) and its struct."""
+
+    def __init__(self, c: dict, device="cuda"):
+        import numpy as np
+        import torch
+        self.lamps = torch.as_tensor(np.ascontiguousarray(c["lamps"], dtype=np.float32)).to(device)
+        ny, nx = self.lamps.shape[:2]
+        self.c = PgCeiling(float(c["z"]), float(c["period"]), float(c["x0"]), float(c["y0"]), float(c["ambient"]),
+                           nx, ny, self.lamps.data_ptr())
+
+
+def _position(t, view):
+    import torch
+    _require(t, torch.float32, "position")
+    if t is None or tuple(t.shape) != (3, view.height, view.width):
+        raise ValueError(f"position must be a (3, {view.height}, {view.width}) device tensor")
+    return _ptr(t)
+
+
+def _hit(t, samples):
+    import torch
+    _require(t, torch.float32, "hit_dist")
+    if t is None or tuple(t.shape) != (samples.spp, samples.height, samples.width):
+        raise ValueError(f"hit_dist must be a ({samples.spp}, {samples.height}, {samples.width}) device tensor")
+    return _ptr(t)
+
+
+def light_ceiling(ceiling: Ceiling, view: View, position, samples: Samples, hit_dist):
+    _samples_fit(samples, view)
+    _check(lib().pg_light_ceiling(C.byref(ceiling.c), C.byref(view.c), _position(position, view),
+                                  C.byref(samples.c), _hit(hit_dist, samples), _stream()), "pg_light_ceiling")
+
+
+def em_update_vpl(p: PgParams, lobes: int, view: View, position, samples: Samples, hit_dist, gamma):
+    _samples_fit(samples, view)
+    _check(lib().pg_em_update_vpl(C.byref(p), lobes, C.byref(view.c), _position(position, view),
+                                  C.byref(samples.c), _hit(hit_dist, samples),
+                                  _lobes_state(gamma, lobes, "gamma", view), _stream()), "pg_em_update_vpl")
 
 
 def philox(counters, seed: int):

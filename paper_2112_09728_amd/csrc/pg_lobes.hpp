@@ -274,12 +274,27 @@ struct LobesCtx {
   Pixel px;
   Gauss G[K];
   float pi[K], one_m_tot;
+  V3 xp;  // positional reuse: the pixel's position relative to the tile's reference point
 };
 
-template <int K>
+// With VPL, a record with r.w > 0 holds its virtual point light y (relative
+// to the tile's reference point) and trains along y - x_p; r.w < 0 marks a
+// sample without an interaction, trained along its own direction with weight
+// -r.w.
+template <int K, bool VPL = false>
 __device__ __forceinline__ void lobes_visit(const LobesCtx<K> &c, float4 r, float &B0, Accum a[K]) {
   if (r.w == 0.0f) return;
-  const V3 l = to_local(c.px.f, V3{r.x, r.y, r.z});
+  V3 wd = V3{r.x, r.y, r.z};
+  if (VPL) {
+    if (r.w > 0.0f) {
+      wd = V3{r.x - c.xp.x, r.y - c.xp.y, r.z - c.xp.z};
+      if (!(dot3(wd, wd) > 0.0f)) return;
+      wd = normalized(wd);
+    } else {
+      r.w = -r.w;
+    }
+  }
+  const V3 l = to_local(c.px.f, wd);
   if (l.z <= 0.0f) return;
   float ux, uy, f, pb;
   hemi2sq(l, ux, uy);
@@ -312,14 +327,82 @@ __device__ __forceinline__ void lobes_visit(const LobesCtx<K> &c, float4 r, floa
   }
 }
 
+// Staging of a tile's records for positional reuse: like stage_records, but
+// a BRDF record with a finite hit distance t holds its virtual point light
+// y = x_q + t w relative to the tile's reference point c (positions of the
+// image are large; differences of nearby ones are small and exact), and one
+// without an interaction holds its direction with the weight negated.
+template <int TW, int TH>
+__device__ __forceinline__ void stage_records_vpl(const ViewK &v, const SamplesK &S, const float *__restrict__ pos,
+                                                  const float *__restrict__ hit, V3 cref, float4 *lds, int tx0,
+                                                  int ty0) {
+  constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH, NT = TW * TH;
+  constexpr int IT = (SA + NT - 1) / NT;
+  const int plane = v.H * v.pitch;
+  const int splane = S.spp * plane;
+  int gi[IT];
+  bool in[IT];
+  V3 xq[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int e = threadIdx.x + i * NT;
+    const int sy = (int)(((float)e + 0.5f) * (1.0f / SW));
+    const int sx = e - sy * SW;
+    const int gx = tx0 - kR + sx, gy = ty0 - kR + sy;
+    in[i] = e < SA && gx >= 0 && gy >= 0 && gx < v.W && gy < v.H;
+    gi[i] = gy * v.pitch + gx;
+    xq[i] = V3{0.0f, 0.0f, 0.0f};
+    if (in[i]) xq[i] = V3{pos[gi[i]] - cref.x, pos[plane + gi[i]] - cref.y, pos[2 * plane + gi[i]] - cref.z};
+  }
+  for (int s = 0; s < S.spp; ++s) {
+    uint8_t st[IT];
+    float px[IT], py[IT], pz[IT], pl[IT], pp[IT], th[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      st[i] = 0;
+      px[i] = py[i] = pz[i] = pl[i] = pp[i] = th[i] = 0.0f;
+      if (in[i]) {
+        const int o = s * plane + gi[i];
+        st[i] = S.strat[o];
+        pp[i] = S.pb[o];
+        px[i] = S.dir[o];
+        py[i] = S.dir[splane + o];
+        pz[i] = S.dir[2 * splane + o];
+        pl[i] = S.L[o];
+        th[i] = hit[o];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int e = threadIdx.x + i * NT;
+      if (IT * NT == SA || e < SA) {
+        const bool ok = st[i] == 1 && pp[i] > 0.0f;
+        const float w = pl[i] * frcp(fmaxf(pp[i], 1.17549435e-38f));
+        float4 r = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (ok) {
+          if (isfinite(th[i])) {
+            const V3 d = normalized(V3{px[i], py[i], pz[i]});
+            r = make_float4(fmaf(th[i], d.x, xq[i].x), fmaf(th[i], d.y, xq[i].y), fmaf(th[i], d.z, xq[i].z), w);
+          } else {
+            r = make_float4(px[i], py[i], pz[i], -w);
+          }
+        }
+        lds[s * SA + e] = r;
+      }
+    }
+  }
+}
+
 // E-step of one pixel over its training list (LDS indices list[j * stride])
 // and the stepwise merge of every lobe, in place on g.  A list whose samples
 // carry no weight leaves g as it is.
-template <int K>
+template <int K, bool VPL = false>
 __device__ __forceinline__ void lobes_update(const ParamsK &P, const ViewK &v, int idx, const float4 *lds,
-                                             const uint16_t *list, int stride, int len, float g[6 * K + 2]) {
+                                             const uint16_t *list, int stride, int len, float g[6 * K + 2],
+                                             V3 xp = V3{0.0f, 0.0f, 0.0f}) {
   const int plane = v.H * v.pitch;
   LobesCtx<K> c;
+  c.xp = xp;
   c.px = make_pixel(P, load3(v.n, plane, idx), load3(v.o, plane, idx), v.rough[idx], v.alb[idx]);
   float tot = 0.0f;
 #pragma unroll
@@ -333,7 +416,7 @@ __device__ __forceinline__ void lobes_update(const ParamsK &P, const ViewK &v, i
   Accum a[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) a[j] = Accum{0, 0, 0, 0, 0, 0, 0};
-  for (int j = 0; j < len; ++j) lobes_visit<K>(c, lds[list[j * stride]], B0, a);
+  for (int j = 0; j < len; ++j) lobes_visit<K, VPL>(c, lds[list[j * stride]], B0, a);
   if (!(B0 > 0.0f)) return;
   const float Wv = g[6 * K], kk = g[6 * K + 1];
   const float eta = frcp(kk + 1.0f);
@@ -385,9 +468,13 @@ __device__ __forceinline__ void lobes_update(const ParamsK &P, const ViewK &v, i
 // and the stepwise merge of every lobe.
 // Dynamic LDS: records [spp][SH][SW] float4, then lists [spp + 20][NT]
 // uint16; the write-back reuses it ([6K + 2][NT] float).
-template <int K, int TW, int TH>
+// With VPL, positions [3][H*pitch] and hit distances [spp][H*pitch] give the
+// positional reuse of virtual point lights (the training directions of every
+// pixel are re-derived from the staged y).
+template <int K, int TW, int TH, bool VPL = false>
 __global__ __launch_bounds__(TW *TH) void k_lobes_em(ParamsK P, ViewK v, SamplesK S, float *__restrict__ gamma,
-                                                     int tiles_x, int n_tiles) {
+                                                     int tiles_x, int n_tiles, const float *__restrict__ pos,
+                                                     const float *__restrict__ hit) {
   constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH, NT = TW * TH;
   extern __shared__ float4 lds[];
   __shared__ EmShared<NT> sh;
@@ -409,7 +496,14 @@ __global__ __launch_bounds__(TW *TH) void k_lobes_em(ParamsK P, ViewK v, Samples
         ncand = spp + n_picks(P, (int)gamma[(6 * K + 1) * plane + idx0]);
     }
   }
-  stage_records<TW, TH>(v, S, lds, tx0, ty0, 0);
+  V3 cref = V3{0.0f, 0.0f, 0.0f};
+  if (VPL) {
+    const int ci = min(ty0, v.H - 1) * v.pitch + min(tx0, v.W - 1);
+    cref = load3(pos, plane, ci);
+    stage_records_vpl<TW, TH>(v, S, pos, hit, cref, lds, tx0, ty0);
+  } else {
+    stage_records<TW, TH>(v, S, lds, tx0, ty0, 0);
+  }
   sh.work[t] = (uint8_t)ncand;
   __syncthreads();
   int me;
@@ -429,7 +523,9 @@ __global__ __launch_bounds__(TW *TH) void k_lobes_em(ParamsK P, ViewK v, Samples
   if (len > 0) {  // otherwise no training sample (or no pixel): the model stays as it is
     const int idx = (ty0 + me / TW) * v.pitch + tx0 + me % TW;
     lobes_load<K>(gamma, plane, idx, g);
-    lobes_update<K>(P, v, idx, lds, list + me, NT, len, g);
+    V3 xp = V3{0.0f, 0.0f, 0.0f};
+    if (VPL) xp = V3{pos[idx] - cref.x, pos[plane + idx] - cref.y, pos[2 * plane + idx] - cref.z};
+    lobes_update<K, VPL>(P, v, idx, lds, list + me, NT, len, g, xp);
   }
   // write-back in natural order through LDS (full cache lines), over the
   // records and lists once no lane reads them
@@ -445,6 +541,61 @@ __global__ __launch_bounds__(TW *TH) void k_lobes_em(ParamsK P, ViewK v, Samples
     const int idx0 = y0 * v.pitch + x0;
 #pragma unroll
     for (int c = 0; c < 6 * K + 2; ++c) gamma[c * plane + idx0] = wb[c * NT + t];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Near-field stand-in for the trace: an emitting plane z = z_c whose emission
+// is a lattice of Gaussian lamps (sx, sy, r, c) summed over the 3x3 cells
+// around the hit point; writes the radiance and the hit distance of every
+// live sample (+inf and the ambient term for a ray that does not rise).
+struct CeilingK {
+  float z, period, x0, y0, ambient;
+  int nx, ny;
+  const float *lamps;
+};
+
+__device__ __forceinline__ float ceiling_emission(const CeilingK &C, float yx, float yy) {
+  const float fx = (yx - C.x0) / C.period, fy = (yy - C.y0) / C.period;
+  float E = C.ambient;
+  if (!(fx >= -1.0f && fx < (float)C.nx + 1.0f && fy >= -1.0f && fy < (float)C.ny + 1.0f)) return E;
+  const int ci = (int)floorf(fx), cj = (int)floorf(fy);
+  for (int dj = -1; dj <= 1; ++dj)
+    for (int di = -1; di <= 1; ++di) {
+      const int i = ci + di, j = cj + dj;
+      if (i < 0 || j < 0 || i >= C.nx || j >= C.ny) continue;
+      const float4 l = reinterpret_cast<const float4 *>(C.lamps)[j * C.nx + i];
+      const float dx = yx - l.x, dy = yy - l.y;
+      E = fmaf(l.w, expf(-(dx * dx + dy * dy) / (2.0f * l.z * l.z)), E);
+    }
+  return E;
+}
+
+__global__ __launch_bounds__(256) void k_light_ceiling(CeilingK C, ViewK v, const float *__restrict__ pos,
+                                                       SamplesK S, float *__restrict__ hit) {
+  int x, y;
+  stream_xy(v.W, v.H, x, y);
+  if (x >= v.W || y >= v.H) return;
+  const int plane = v.H * v.pitch;
+  const int idx = y * v.pitch + x;
+  const int splane = S.spp * plane;
+  const V3 xp = load3(pos, plane, idx);
+  for (int s = 0; s < S.spp; ++s) {
+    const int r = (s * v.H + y) * v.pitch + x;
+    const uint8_t code = S.strat[r];
+    float L = 0.0f, t = 0.0f;
+    if (code == 1 || code == 2) {
+      const V3 w = normalized(V3{S.dir[r], S.dir[splane + r], S.dir[2 * splane + r]});
+      if (w.z > 0.0f) {
+        t = (C.z - xp.z) / w.z;
+        L = ceiling_emission(C, fmaf(t, w.x, xp.x), fmaf(t, w.y, xp.y));
+      } else {
+        t = __builtin_inff();
+        L = C.ambient;
+      }
+    }
+    S.L[r] = L;
+    hit[r] = t;
   }
 }
 

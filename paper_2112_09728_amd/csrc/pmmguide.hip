@@ -609,12 +609,68 @@ pg_status pg_em_update_lobes(const pg_params *p, int32_t lobes, const pg_view *v
     constexpr int K = decltype(kc)::value;
     if (TH == 8)
       hipLaunchKernelGGL((k_lobes_em<K, 32, 8>), dim3(tx * ty), dim3(256), lds, s, P, V, S, gamma_inout, tx,
-                         tx * ty);
+                         tx * ty, nullptr, nullptr);
     else
       hipLaunchKernelGGL((k_lobes_em<K, 32, 4>), dim3(tx * ty), dim3(128), lds, s, P, V, S, gamma_inout, tx,
-                         tx * ty);
+                         tx * ty, nullptr, nullptr);
     return check_launch("pg_em_update_lobes");
   });
+}
+
+pg_status pg_em_update_vpl(const pg_params *p, int32_t lobes, const pg_view *v, const float *position,
+                           const pg_samples *in, const float *hit_dist, float *gamma_inout, void *stream) {
+  pg_status st;
+  if ((st = check_params(p)) || (st = check_view(v, "view", true)) || (st = check_lobes(p, lobes, v)) ||
+      (st = check_samples(in, false, true)))
+    return st;
+  if (!gamma_inout) return fail(PG_ERR_ARG, "gamma is NULL");
+  if (!position || !hit_dist) return fail(PG_ERR_ARG, "position and hit_dist are required");
+  const ParamsK P = to_k(p);
+  const ViewK V = to_k(v);
+  const SamplesK S = to_k(in);
+  hipStream_t s = (hipStream_t)stream;
+  const int TH = in->spp > 4 ? 4 : 8;
+  const int tx = (V.W + 31) / 32, ty = (V.H + TH - 1) / TH;
+  const size_t lds_tile = (size_t)in->spp * (32 + 2 * kR) * (TH + 2 * kR) * sizeof(float4) +
+                          (size_t)(in->spp + 20) * 32 * TH * sizeof(uint16_t);
+  const size_t lds_wb = (size_t)(6 * lobes + 2) * 32 * TH * sizeof(float);
+  const size_t lds = lds_tile > lds_wb ? lds_tile : lds_wb;
+  return dispatch_lobes(lobes, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    if (TH == 8)
+      hipLaunchKernelGGL((k_lobes_em<K, 32, 8, true>), dim3(tx * ty), dim3(256), lds, s, P, V, S, gamma_inout,
+                         tx, tx * ty, position, hit_dist);
+    else
+      hipLaunchKernelGGL((k_lobes_em<K, 32, 4, true>), dim3(tx * ty), dim3(128), lds, s, P, V, S, gamma_inout,
+                         tx, tx * ty, position, hit_dist);
+    return check_launch("pg_em_update_vpl");
+  });
+}
+
+pg_status pg_light_ceiling(const pg_ceiling *c, const pg_view *v, const float *position, const pg_samples *samples,
+                           float *hit_dist, void *stream) {
+  pg_status st;
+  if ((st = check_view(v, "view", false)) || (st = check_samples(samples, false, true))) return st;
+  if (!c || !c->lamps) return fail(PG_ERR_ARG, "ceiling and its lamps are required");
+  if (c->nx < 1 || c->ny < 1 || (int64_t)c->nx * c->ny > (1 << 24))
+    return fail(PG_ERR_ARG, "lamp lattice %d x %d invalid", c->nx, c->ny);
+  if (!(c->period > 0.0f)) return fail(PG_ERR_ARG, "period must be > 0");
+  if (!position || !hit_dist) return fail(PG_ERR_ARG, "position and hit_dist are required");
+  if (((uintptr_t)c->lamps & 15u) != 0) return fail(PG_ERR_ARG, "lamps must be 16-byte aligned");
+  CeilingK C;
+  C.z = c->z;
+  C.period = c->period;
+  C.x0 = c->x0;
+  C.y0 = c->y0;
+  C.ambient = c->ambient;
+  C.nx = c->nx;
+  C.ny = c->ny;
+  C.lamps = c->lamps;
+  const ViewK V = to_k(v);
+  const SamplesK S = to_k(samples);
+  hipLaunchKernelGGL(k_light_ceiling, stream_grid(V.W, V.H), dim3(64, 4), 0, (hipStream_t)stream, C, V, position, S,
+                     hit_dist);
+  return check_launch("pg_light_ceiling");
 }
 
 pg_status pg_pdf_lobes(const pg_params *p, int32_t lobes, const pg_view *v, const float *gamma, int32_t n_per_px,

@@ -161,6 +161,38 @@ def test_lobes_argument_errors_before_launch():
         assert msg, fn.__name__
 
 
+@no_device
+def test_vpl_argument_errors_before_launch():
+    L = pg.lib()
+    P = pg.params(1, frame=1)
+    v = _view()
+    s = _samples()
+    c = pg.PgCeiling(32.0, 48.0, -48.0, -48.0, 0.05, 4, 3, FAKE)
+    cases = [
+        (L.pg_em_update_vpl, (C.byref(P), 1, C.byref(v), None, C.byref(s), FAKE, FAKE, None), pg.PG_ERR_ARG),
+        (L.pg_em_update_vpl, (C.byref(P), 1, C.byref(v), FAKE, C.byref(s), None, FAKE, None), pg.PG_ERR_ARG),
+        (L.pg_em_update_vpl, (C.byref(P), 0, C.byref(v), FAKE, C.byref(s), FAKE, FAKE, None), pg.PG_ERR_ARG),
+        (L.pg_em_update_vpl, (C.byref(P), 1, C.byref(v), FAKE, C.byref(s), FAKE, None, None), pg.PG_ERR_ARG),
+        (L.pg_em_update_vpl, (C.byref(pg.params(1, flags=pg.PG_EM_BATCH)), 1, C.byref(v), FAKE, C.byref(s), FAKE,
+                              FAKE, None), pg.PG_ERR_UNSUPPORTED),
+        (L.pg_light_ceiling, (None, C.byref(v), FAKE, C.byref(s), FAKE, None), pg.PG_ERR_ARG),
+        (L.pg_light_ceiling, (C.byref(pg.PgCeiling(32.0, 48.0, 0, 0, 0.05, 0, 3, FAKE)), C.byref(v), FAKE,
+                              C.byref(s), FAKE, None), pg.PG_ERR_ARG),
+        (L.pg_light_ceiling, (C.byref(pg.PgCeiling(32.0, 0.0, 0, 0, 0.05, 4, 3, FAKE)), C.byref(v), FAKE,
+                              C.byref(s), FAKE, None), pg.PG_ERR_ARG),
+        (L.pg_light_ceiling, (C.byref(pg.PgCeiling(32.0, 48.0, 0, 0, 0.05, 4, 3, FAKE + 4)), C.byref(v), FAKE,
+                              C.byref(s), FAKE, None), pg.PG_ERR_ARG),
+        (L.pg_light_ceiling, (C.byref(c), C.byref(v), None, C.byref(s), FAKE, None), pg.PG_ERR_ARG),
+        (L.pg_light_ceiling, (C.byref(c), C.byref(v), FAKE, C.byref(s), None, None), pg.PG_ERR_ARG),
+        (L.pg_light_ceiling, (C.byref(c), C.byref(v), FAKE, C.byref(_samples(radiance=False)), FAKE, None),
+         pg.PG_ERR_ARG),
+    ]
+    for fn, args, want in cases:
+        st, msg = _status(fn, *args)
+        assert st == want, (fn.__name__, st, msg)
+        assert msg, fn.__name__
+
+
 def test_pick_division_identity():
     """The training kernel divides a pick code c < 48 spp by spp as
     (c * ceil(2^16/spp)) >> 16; exact for every code it can meet."""
