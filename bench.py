@@ -92,6 +92,8 @@ def parse():
     ap.add_argument("--tile", default=None, help="training tile WxH (default: the library's)")
     ap.add_argument("--lobes", type=int, default=1,
                     help="Gaussian lobes per pixel; above 1 the K-lobe calls run (FP32 state, fused)")
+    ap.add_argument("--vpl", action="store_true",
+                    help="positional reuse of virtual point lights under the near-field ceiling (K-lobe calls)")
     ap.add_argument("--workload", default="1080p", choices=["1080p", "batched16"],
                     help="1080p: the single-view path (default); batched16: 16 uneven views, "
                          "FP16 Gamma, batched frame (eager and graph-replayed) against 16 plain "
@@ -120,11 +122,12 @@ def main():
     seed = cfg["seed"] if a.seed is None else a.seed
     W, H, S = a.width, a.height, a.spp
     K = a.lobes
-    if K != 1 and (a.gamma_dtype != "f32" or a.unfused or a.tile):
+    lobes_path = K != 1 or a.vpl
+    if lobes_path and (a.gamma_dtype != "f32" or a.unfused or a.tile):
         print("bench.py: the K-lobe calls take an FP32 state, fused, with their own tile", file=sys.stderr)
         sys.exit(2)
     dt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[a.gamma_dtype]
-    G = (32 if a.gamma_dtype == "f32" else 16) if K == 1 else 4 * (6 * K + 2)
+    G = (32 if a.gamma_dtype == "f32" else 16) if not lobes_path else 4 * (6 * K + 2)
     frames = a.warmup + a.steps
     t0 = time.time()
     seq = wl.Sequence(W, H, seed, moving=True)
@@ -137,11 +140,14 @@ def main():
     over = {}
     if a.tile:
         over["tile_w"], over["tile_h"] = (int(v) for v in a.tile.lower().split("x"))
-    if K == 1:
+    if not lobes_path:
         guide = pg.Guide(W, H, lights, ambient, spp=S, seed=seed, gamma_dtype=dt, fused=not a.unfused,
                          **over)
     else:
         guide = pg.LobesGuide(W, H, lights, ambient, lobes=K, spp=S, seed=seed)
+    if a.vpl:
+        ceiling = pg.Ceiling(seq.world["ceiling"])
+        hit = torch.empty((S, H, W), dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     print(f"bench: setup {time.time() - t0:.1f} s ({W}x{H}, spp {S}, Gamma {a.gamma_dtype}, "
           f"{frames} frames resident on the device)", file=sys.stderr, flush=True)
@@ -153,7 +159,7 @@ def main():
         g_prev, g_out = guide.gamma[guide.cur], guide.gamma[1 - guide.cur]
         if ev is not None:
             ev[0].record()
-        if K > 1:
+        if lobes_path:
             pg.reproject_sample_lobes(p, K, cur, prev, g_prev if t else None, g_out, guide.samples)
         elif a.unfused:
             pg.reproject(p, cur, prev, g_prev if t else None, g_out)
@@ -162,10 +168,15 @@ def main():
             pg.reproject_sample(p, cur, prev, g_prev if t else None, g_out, guide.samples)
         if ev is not None:
             ev[1].record()
-        pg.light_field(guide.lights, cur, dev_frames[t].vis, guide.samples)
+        if a.vpl:
+            pg.light_ceiling(ceiling, cur, dev_frames[t].position, guide.samples, hit)
+        else:
+            pg.light_field(guide.lights, cur, dev_frames[t].vis, guide.samples)
         if ev is not None:
             ev[2].record()
-        if K > 1:
+        if a.vpl:
+            pg.em_update_vpl(p, K, cur, dev_frames[t].position, guide.samples, hit, g_out)
+        elif lobes_path:
             pg.em_update_lobes(p, K, cur, guide.samples, g_out)
         else:
             pg.em_update(p, cur, guide.samples, g_out)
@@ -201,6 +212,8 @@ def main():
     px = W * H
     mpix = px / (ms * 1e-3) / 1e6
     b_rs, b_em = bytes_reproject_sample(G, S), bytes_em(G, S)
+    if a.vpl:
+        b_em += 12 + 4 * S  # positions and hit distances
     b_path = b_rs + b_em
     em_gbs = b_em * px / (em.mean() * 1e-3) / 1e9
     rs_gbs = b_rs * px / (rs.mean() * 1e-3) / 1e9
@@ -211,9 +224,10 @@ def main():
     # committed rocprofv3 summaries of this workload (null when the kernel
     # sources have changed since, or for another workload)
     # summaries exist for the default workload at 1 and 2 lobes
-    default = (W, H, S, a.gamma_dtype, a.tile, a.unfused) == (1920, 1080, 1, "f32", None, False) and K in (1, 2)
-    tag = "" if K == 1 else f"_k{K}"
-    if K == 1:
+    default = (W, H, S, a.gamma_dtype, a.tile, a.unfused) == (1920, 1080, 1, "f32", None, False) and \
+        (K, a.vpl) in ((1, False), (2, False), (1, True))
+    tag = "_vpl" if a.vpl else ("" if K == 1 else f"_k{K}")
+    if not lobes_path:
         dom_name = "k_em" if dominant == "em" else "k_reproject_sample"
     else:
         dom_name = "k_lobes_em" if dominant == "em" else "k_lobes_reproject_sample"
@@ -239,7 +253,7 @@ def main():
 
     cpu = None
     if a.cpu_baseline_seconds > 0:
-        cpu = cpu_baseline(seed, S, W, H, a.cpu_baseline_seconds, K)
+        cpu = cpu_baseline(seed, S, W, H, a.cpu_baseline_seconds, K, a.vpl)
 
     out = {
         "metric": "ms/frame & Mpix/s for reproject+sample+EM at 1080p 1spp; % of HBM roofline",
@@ -258,8 +272,9 @@ def main():
             "workload": f"{W}x{H} spp{S}, {frames}-frame camera-pan sequence "
                         f"(timed frames {a.warmup}..{frames - 1}), Gamma {a.gamma_dtype}, "
                         f"{'unfused' if a.unfused else 'fused reproject+sample'}"
-                        + (f", {K} Gaussian lobes per pixel" if K > 1 else ""),
-            "width": W, "height": H, "spp": S, "gamma_storage": a.gamma_dtype, "lobes": K,
+                        + (f", {K} Gaussian lobes per pixel" if K > 1 else "")
+                        + (", positional reuse of virtual point lights under the near-field ceiling" if a.vpl else ""),
+            "width": W, "height": H, "spp": S, "gamma_storage": a.gamma_dtype, "lobes": K, "vpl": a.vpl,
         },
         "roofline": {
             "bound": "hbm",
@@ -390,7 +405,7 @@ def bench_batched(a):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(seed, spp, W, H, budget_s, lobes=1):
+def cpu_baseline(seed, spp, W, H, budget_s, lobes=1, vpl=False):
     """The FP64 oracle's reproject + sample + EM on the host cores (light field
     excluded like on the GPU): whole frames of the same sequence from frame 0
     until the time budget is spent (the K-lobe functions when lobes > 1)."""
@@ -408,17 +423,24 @@ def cpu_baseline(seed, spp, W, H, budget_s, lobes=1):
         v = O.OView(fr, fr["motion"], fr["disocc"])
         P = O.params(seed, frame=n)
         t0 = time.time()
-        if lobes == 1:
+        if lobes == 1 and not vpl:
             g1, _ = O.reproject(P, v, v_prev if v_prev is not None else v, gamma)
             rec = O.sample(P, v, g1, spp)
         else:
             g1, _ = O.reproject_k(P, lobes, v, v_prev if v_prev is not None else v, gamma)
             rec = O.sample_k(P, lobes, v, g1, spp)
         t1 = time.time()
-        rec["radiance"] = O.light(fr["lights"], float(fr["ambient"]), fr["vis"], rec["dir"],
-                                  rec["strategy"])
+        if vpl:
+            rec["radiance"], rec["hit_dist"] = O.light_ceiling(fr["ceiling"], v, fr["position"], rec["dir"],
+                                                               rec["strategy"])
+        else:
+            rec["radiance"] = O.light(fr["lights"], float(fr["ambient"]), fr["vis"], rec["dir"],
+                                      rec["strategy"])
         t2 = time.time()
-        gamma = O.em(P, v, rec, g1) if lobes == 1 else O.em_k(P, lobes, v, rec, g1)
+        if vpl:
+            gamma = O.em_vpl(P, lobes, v, fr["position"], rec, g1)
+        else:
+            gamma = O.em(P, v, rec, g1) if lobes == 1 else O.em_k(P, lobes, v, rec, g1)
         t3 = time.time()
         spent += (t1 - t0) + (t3 - t2)
         v_prev = v
@@ -433,7 +455,8 @@ def cpu_baseline(seed, spp, W, H, budget_s, lobes=1):
         "cores": O.num_threads(),
         "kind": "oracle",
         "sample": f"frames 0..{n - 1} of the same {W}x{H} spp{spp} pan sequence"
-                  + (f" at {lobes} lobes" if lobes > 1 else "") + ", whole frames "
+                  + (f" at {lobes} lobes" if lobes > 1 else "") + (" with positional reuse" if vpl else "")
+                  + ", whole frames "
                   f"({time.time() - t_all:.0f} s wall incl. the untimed light field)",
     }
 
