@@ -108,6 +108,7 @@ def _declare(L):
     L.orc_light_ceiling.argtypes = [P, P, P, i32, P, P, P, P, Rect]
     L.orc_reference_ceiling.argtypes = [P, P, P, P, i32, P, i64, P, P]
     L.orc_num_threads.restype = i32
+    L.orc_set_num_threads.argtypes = [i32]
 
 
 def _ptr(a):
@@ -476,6 +477,10 @@ def reference_ceiling(P, view, position, ceil, pixels, n_samples=16384):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    lib().orc_set_num_threads(int(n))
 
 
 class Frames:

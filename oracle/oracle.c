@@ -1600,3 +1600,12 @@ int32_t orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Threads of the following parallel regions (timing of the baseline). */
+void orc_set_num_threads(int32_t n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}

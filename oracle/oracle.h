@@ -162,6 +162,7 @@ void orc_light_ceiling(const orc_ceiling *C, const orc_view *v, const float *pos
 void orc_reference_ceiling(const orc_params *P, const orc_view *v, const float *position, const orc_ceiling *C,
                            int32_t n_pixels, const int64_t *pixels, int64_t n, double *mean, double *stderr_out);
 int32_t orc_num_threads(void);
+void orc_set_num_threads(int32_t n);
 
 #ifdef __cplusplus
 }
