@@ -213,3 +213,56 @@ def test_vpl_study_1080p_pan_under_the_ceiling():
     say(f"  mean rel. MSE: directions reused {mean['dir']:.4f}, positions reused {mean['pos']:.4f}")
     assert all(np.isfinite(v) for r in rows for v in r.values())
     assert mean["pos"] <= 1.1 * mean["dir"], mean
+
+
+def test_1080p_pan_vpl_sampled_crops():
+    """The 1080p pan under the ceiling with positional reuse (one lobe, the
+    launches bench.py --vpl times) for 6 frames; on frame 5 the ceiling
+    field and the update of 32 crops of 16x16 pixels are recomputed by the
+    oracle from the GPU's inputs."""
+    W, H, spp, K = 1920, 1080, 1, 1
+    seed = wl.CONFIGS["1080p_spp1_64f_fp32_pan"]["seed"]
+    say("case: 1080p pan under the ceiling, positional reuse, sampled crops")
+    seq = wl.Sequence(W, H, seed)
+    fr = seq.frame(0)
+    ceil = pg.Ceiling(fr["ceiling"])
+    s = pg.Samples(spp, H, W)
+    hit = torch.empty((spp, H, W), dtype=torch.float32, device="cuda")
+    gam = [pg.new_lobes_gamma(K, H, W), pg.new_lobes_gamma(K, H, W)]
+    prev = None
+    T = 6
+    for t in range(T):
+        if t:
+            fr = seq.frame(t)
+        cur = pg.DeviceFrame(fr)
+        p = pg.params(seed, frame=t)
+        g_in, g_out = gam[t % 2], gam[1 - t % 2]
+        pg.reproject_sample_lobes(p, K, cur.view, prev.view if t else None, g_in if t else None, g_out, s)
+        pg.light_ceiling(ceil, cur.view, cur.position, s, hit)
+        if t == T - 1:
+            torch.cuda.synchronize()
+            g_rs = host(g_out).astype(np.float64)
+        pg.em_update_vpl(p, K, cur.view, cur.position, s, hit, g_out)
+        prev = cur
+    torch.cuda.synchronize()
+    g_em = host(gam[T % 2])
+    rec = {k_: (a.astype(np.float64) if a.dtype == np.float32 else a) for k_, a in records_host(s).items()}
+    rec["hit_dist"] = host(hit).astype(np.float64)
+    P = O.params(seed, frame=T - 1)
+    v = O.OView(fr, fr["motion"], fr["disocc"])
+    rng = np.random.default_rng(seed + 5)
+    worst = {}
+    for c in range(32):
+        x0, y0 = int(rng.integers(0, W - 16)), int(rng.integers(0, H - 16))
+        rect = (x0, y0, x0 + 16, y0 + 16)
+        sl = (slice(None), slice(y0, y0 + 16), slice(x0, x0 + 16))
+        L_o, t_o = O.light_ceiling(fr["ceiling"], v, fr["position"], rec["dir"], rec["strategy"], rect=rect)
+        live = ((rec["strategy"] == 1) | (rec["strategy"] == 2))[sl]
+        fin = live & np.isfinite(t_o[sl]) & np.isfinite(rec["hit_dist"][sl])
+        assert rel_err(rec["hit_dist"][sl][fin], t_o[sl][fin]).max(initial=0) <= 1e-5
+        assert rel_err(rec["radiance"][sl][live], L_o[sl][live]).max(initial=0) <= 1e-3
+        g2, stats = O.em_vpl(P, K, v, fr["position"], rec, g_rs, rect=rect, with_stats=True)
+        e = assert_gamma_close(g_em[sl], g2[sl], TOL_EM_FRAME, mask=~lobes_underflow(stats[sl]), what=f"crop {c}")
+        for k_, v_ in e.items():
+            worst[k_] = max(worst.get(k_, 0.0), v_)
+    say(f"  32 crops of frame {T - 1}: worst {worst}")
