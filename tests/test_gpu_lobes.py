@@ -410,3 +410,52 @@ def test_lobes_study_1080p_pan():
     say(f"  mean rel. MSE over frames {evals[1:]}: " + ", ".join(f"K={k} {v:.4f}" for k, v in mean.items()))
     assert all(np.isfinite(v) for r in rows for v in r[1].values())
     assert mean[2] <= 1.1 * mean[1] and mean[3] <= 1.1 * mean[1], mean
+
+
+# ------------------------------------------------------------------ edge cases
+@pytest.mark.parametrize("K,W,H,spp", [(2, 1, 1, 1), (3, 70, 1, 2), (2, 1, 37, 3), (4, 45, 13, 8), (1, 33, 9, 8)])
+def test_degenerate_shapes_and_largest_lds(K, W, H, spp):
+    """1x1, one row, one column, and spp 8 at K = 4 (the largest LDS request
+    of the training kernel): reprojection + sampling and the update against
+    the oracle, a NaN history resetting, and the positional variant with
+    finite hit distances."""
+    say(f"case: lobes edge K {K} {W}x{H} spp {spp}")
+    seed = 15000 + K + W + H + spp
+    scene = wl.make_scene(W, H, seed)
+    rng = np.random.default_rng(seed)
+    g_prev = random_lobes(K, H, W, rng, k_lo=1)
+    g_prev[0, 0, 0] = np.nan
+    mv, mask = wl.make_motion(W, H, seed, 2)
+    p, P = _p(seed, 2)
+    cur, prev = gpu_view(scene, dev(mv), dev(mask)), gpu_view(scene)
+    go = torch.empty_like(dev(g_prev))
+    s = pg.Samples(spp, H, W)
+    pg.reproject_sample_lobes(p, K, cur, prev, dev(g_prev), go, s)
+    pg.light_field(pg.lights_struct(scene["lights"], float(scene["ambient"])), cur, dev(scene["vis"]), s)
+    torch.cuda.synchronize()
+    gg = host(go)
+    vo = O.OView(scene, mv, mask)
+    g_o, src_o = O.reproject_k(P, K, vo, O.OView(scene), g_prev)
+    assert np.isfinite(gg).all()
+    both = (src_o >= 0) & ~_is_reset(gg, K, P)
+    for j in range(K):
+        assert np.abs(gg[6 * j:6 * j + 2, both] - g_o[6 * j:6 * j + 2, both]).max(initial=0) <= TOL_DIR
+    compare_records(records_host(s), O.sample_k(P, K, vo, gg, spp), f"K {K} {W}x{H}")
+    g_in = gg.copy()
+    gt = dev(g_in)
+    pg.em_update_lobes(p, K, cur, s, gt)
+    torch.cuda.synchronize()
+    g_e, stats = O.em_k(P, K, vo, records_host(s), g_in, with_stats=True)
+    for j, (a, b) in enumerate(zip(lobe_slices(host(gt), K), lobe_slices(g_e, K))):
+        assert_gamma_quantile(a, b, TOL_EM_FRAME, TOL_EM_RUN, mask=~lobes_underflow(stats), what=f"lobe {j}")
+    # positional reuse on a flat grid of positions with finite hit distances
+    pos = np.stack(list(np.meshgrid(np.arange(W) + 0.5, np.arange(H) + 0.5)) + [np.zeros((H, W))]).astype(np.float32)
+    hit = rng.uniform(5.0, 50.0, (spp, H, W)).astype(np.float32)
+    gv = dev(g_in)
+    pg.em_update_vpl(p, K, cur, dev(pos), s, dev(hit), gv)
+    torch.cuda.synchronize()
+    rec = records_host(s)
+    rec["hit_dist"] = hit
+    g_v, stats = O.em_vpl(P, K, vo, pos, rec, g_in, with_stats=True)
+    for j, (a, b) in enumerate(zip(lobe_slices(host(gv), K), lobe_slices(g_v, K))):
+        assert_gamma_quantile(a, b, TOL_EM_FRAME, TOL_EM_RUN, mask=~lobes_underflow(stats), what=f"vpl lobe {j}")
