@@ -38,6 +38,13 @@ def bytes_reproject_sample(G, S):
     return 57 + 2 * G + 21 * S
 
 
+def bytes_reproject_then_sample(G, S):
+    """The two launches unfused: reprojection 57 + 2G (writes Gamma'), then
+    sampling re-reads Gamma' G, n 12, omega_o 12, roughness 4 and writes the
+    records 21 S."""
+    return 85 + 3 * G + 21 * S
+
+
 def bytes_em(G, S):
     return 2 * G + 32 + 21 * S
 
@@ -222,7 +229,7 @@ def main():
     ms = float(path.mean())
     px = W * H
     mpix = px / (ms * 1e-3) / 1e6
-    b_rs, b_em = bytes_reproject_sample(G, S), bytes_em(G, S)
+    b_rs, b_em = (bytes_reproject_then_sample(G, S) if a.unfused else bytes_reproject_sample(G, S)), bytes_em(G, S)
     if a.vpl:
         b_em += 12 + 4 * S  # positions and hit distances
     b_path = b_rs + b_em
