@@ -340,15 +340,16 @@ size_t pg_batch_table_bytes(int32_t n_views);
 pg_status pg_batch_pack(const pg_batch_view *views, int32_t n_views, void *host_table, size_t bytes);
 
 /* Enqueues on `stream`: a copy of `bytes` bytes from host_table to
- * device_table (caller-owned device memory), then the persistent launches
- * (sampling for all views, then training per spp group), which read the
- * table there.  The launch configuration (dtype, spp groups and their tiles)
+ * device_table (caller-owned device memory), then the launches (sampling for
+ * all views, persistent; then training per spp group, one block per tile),
+ * which read the table there.  The launch configuration (dtype, spp groups and their tiles)
  * is read from host_table during the call.  host_table should be pinned
  * (hipHostMalloc) so that the copy is asynchronous and can be captured; it
  * must not be re-packed before the copy has run.  A captured graph replays
  * re-packed tables of other frames and views as long as the dtype and the spp
- * groups with their tiles stay those of the capture (a group that differs is
- * skipped by its kernel: nothing of it is written).  Views must not share
+ * groups with their tiles stay those of the capture and no group has more
+ * training tiles than at the capture (a group that differs is skipped by its
+ * kernel: nothing of it is written).  Views must not share
  * output buffers. */
 pg_status pg_frame_batched(const void *host_table, void *device_table, size_t bytes, void *stream);
 

@@ -1087,12 +1087,14 @@ __global__ __launch_bounds__(256) void k_rs_batched(const char *__restrict__ tab
   }
 }
 
-// Persistent training over the TW x TH tiles of the views of class `cls`:
-// the blocks of XCD j walk the j-th band of the class's tiles.  `spp_cap` is
-// the spp the dynamic LDS was sized for; a table whose class differs from the
-// launch (tile, spp, dtype) is not processed.
+// Training over the TW x TH tiles of the views of class `cls`, one block per
+// tile in XCD bands (like k_em: with no state carried from tile to tile the
+// kernel fits 8 waves/SIMD; a persistent loop over tiles needed ~30 more
+// VGPRs).  `spp_cap` is the spp the dynamic LDS was sized for; a table whose
+// class differs from the launch (tile, spp, dtype, or more tiles than the
+// grid) is not processed.
 template <typename TG, int TW, int TH>
-__global__ __launch_bounds__(TW *TH) void k_em_batched(const char *__restrict__ table, int dtype, int cls,
+__global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TH == 2 ? 1 : 8))) void k_em_batched(const char *__restrict__ table, int dtype, int cls,
                                                        int spp_cap) {
   extern __shared__ float4 lds[];
   __shared__ EmShared<TW * TH> sh;
@@ -1102,18 +1104,18 @@ __global__ __launch_bounds__(TW *TH) void k_em_batched(const char *__restrict__ 
   if (c.spp > spp_cap || c.tile_w != TW || c.tile_h != TH) return;
   const int n_views = hd->n_views;
   const BatchViewK *vs = batch_views(table);
-  const TileBand b(c.em_end - c.em_begin);
-  for (int i = b.first; i < b.end; i += b.step) {
-    __syncthreads();  // the previous tile's write-back has read the LDS
-    const int t = c.em_begin + i;
-    const BatchViewK &bv = vs[batch_find<true>(vs, n_views, t)];
-    const int l = t - bv.em_begin;
-    const int tx0 = (l % bv.em_tiles_x) * TW, ty0 = (l / bv.em_tiles_x) * TH;
-    const ParamsK P = batch_params(hd->base, bv);
-    EmInput<TW, TH> R;
-    em_load(bv.cur, bv.S, (const TG *)bv.gout, tx0, ty0, R);
-    em_tile<TG, TW, TH>(P, bv.cur, bv.S, (TG *)bv.gout, 1, 0, tx0, ty0, t, lds, sh, R);
-  }
+  const int n = c.em_end - c.em_begin;
+  // a class with more tiles than the grid (a replayed launch for other views)
+  // differs from the launch: not processed
+  if (n > (int)gridDim.x || (int)blockIdx.x >= n) return;
+  const int t = c.em_begin + xcd_tile((int)blockIdx.x, n);
+  const BatchViewK &bv = vs[batch_find<true>(vs, n_views, t)];
+  const int l = t - bv.em_begin;
+  const int tx0 = (l % bv.em_tiles_x) * TW, ty0 = (l / bv.em_tiles_x) * TH;
+  const ParamsK P = batch_params(hd->base, bv);
+  EmInput<TW, TH> R;
+  em_load(bv.cur, bv.S, (const TG *)bv.gout, tx0, ty0, R);
+  em_tile<TG, TW, TH>(P, bv.cur, bv.S, (TG *)bv.gout, 1, 0, tx0, ty0, (int)blockIdx.x, lds, sh, R);
 }
 
 // Philox words for given counters (diagnostic entry).

@@ -327,11 +327,9 @@ BatchViewK to_batch(const pg_batch_view &b, int rs_begin, int em_begin, Tile t) 
 template <typename TG, int TW, int TH>
 pg_status launch_em_batched_t(const void *table, int dtype, int cls, int spp, int n_tiles, hipStream_t st) {
   const size_t lds = tile_lds(Tile{TW, TH}, spp);
-  int blocks = 0;
-  pg_status e = persistent_blocks((const void *)k_em_batched<TG, TW, TH>, TW * TH, lds, blocks);
-  if (e) return e;
-  if (blocks > n_tiles) blocks = n_tiles;
-  hipLaunchKernelGGL((k_em_batched<TG, TW, TH>), dim3(blocks), dim3(TW * TH), lds, st, (const char *)table, dtype,
+  if (n_tiles < 1) return PG_OK;
+  // one tile per block, like k_em (the class's tile count is fixed by its views)
+  hipLaunchKernelGGL((k_em_batched<TG, TW, TH>), dim3(n_tiles), dim3(TW * TH), lds, st, (const char *)table, dtype,
                      cls, spp);
   return PG_OK;
 }
