@@ -341,15 +341,16 @@ pg_status pg_batch_pack(const pg_batch_view *views, int32_t n_views, void *host_
 
 /* Enqueues on `stream`: a copy of `bytes` bytes from host_table to
  * device_table (caller-owned device memory), then the launches (sampling for
- * all views, persistent; then training per spp group, one block per tile),
- * which read the table there.  The launch configuration (dtype, spp groups and their tiles)
+ * all views, then training per spp group, one block per tile), which read
+ * the table there.  The launch configuration (dtype, spp groups and their tiles)
  * is read from host_table during the call.  host_table should be pinned
  * (hipHostMalloc) so that the copy is asynchronous and can be captured; it
  * must not be re-packed before the copy has run.  A captured graph replays
  * re-packed tables of other frames and views as long as the dtype and the spp
- * groups with their tiles stay those of the capture and no group has more
- * training tiles than at the capture (a group that differs is skipped by its
- * kernel: nothing of it is written).  Views must not share
+ * groups with their tiles stay those of the capture and the views have no
+ * more sampling tiles, and no group more training tiles, than at the capture
+ * (a launch whose part of the table differs skips it: nothing of it is
+ * written).  Views must not share
  * output buffers. */
 pg_status pg_frame_batched(const void *host_table, void *device_table, size_t bytes, void *stream);
 

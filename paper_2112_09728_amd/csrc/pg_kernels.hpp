@@ -870,20 +870,6 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
   }
 }
 
-// Static persistent schedule: the blocks of XCD j (ids j, j + 8, ...) walk
-// the j-th of 8 contiguous bands of the tile list, so that neighbouring tiles
-// share that XCD's L2.
-struct TileBand {
-  int first, end, step;
-  __device__ TileBand(int n_tiles) {
-    const int G = (int)gridDim.x, nb = G < 8 ? G : 8;
-    const int band = (int)blockIdx.x % nb, slot = (int)blockIdx.x / nb;
-    step = (G - band + nb - 1) / nb;
-    first = (int)((long long)n_tiles * band / nb) + slot;
-    end = (int)((long long)n_tiles * (band + 1) / nb);
-  }
-};
-
 // One tile per block (blocks are mapped to XCD bands by xcd_tile); with the
 // LDS and registers of a tile, several blocks share each CU, which hides the
 // loads of one block behind the arithmetic of the others better than a
@@ -1060,31 +1046,32 @@ __device__ __forceinline__ ParamsK batch_params(const ParamsK &base, const Batch
   return P;
 }
 
-// Persistent reprojection + sampling + light field over the 64x4 pixel tiles
-// of all views, grid-stride.  `dtype` is the launch's Gamma type: a table of
-// another type is not processed.
+// Reprojection + sampling + light field over the 64x4 pixel tiles of all
+// views, one block per tile (a persistent grid-stride loop held 72-80 VGPRs,
+// this 60-62).  `dtype` is the launch's Gamma type: a table of another type,
+// or with more tiles than the grid, is not processed.
 template <typename TG>
 __global__ __launch_bounds__(256) void k_rs_batched(const char *__restrict__ table, int dtype) {
   const BatchHeader *hd = reinterpret_cast<const BatchHeader *>(table);
   if (hd->dtype != dtype) return;
   const int n_views = hd->n_views, n_tiles = hd->rs_tiles;
   const BatchViewK *vs = batch_views(table);
-  // interleaved, not banded: the views are ordered by spp, so contiguous
-  // bands would give one XCD up to 8x the sampling work of another
-  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-    const BatchViewK &bv = vs[batch_find<false>(vs, n_views, t)];
-    const int local = t - bv.rs_begin;
-    const int x = (local % bv.rs_tiles_x) * 64 + (int)(threadIdx.x & 63);
-    const int y = (local / bv.rs_tiles_x) * 4 + (int)(threadIdx.x >> 6);
-    const ViewK cur = bv.cur;
-    if (x >= cur.W || y >= cur.H) continue;
-    const ParamsK P = batch_params(hd->base, bv);
-    ViewK prev = cur;
-    prev.n = bv.prev_n;
-    prev.z = bv.prev_z;
-    reproject_sample_pixel(P, cur, prev, (const TG *)bv.gprev, (TG *)bv.gout, bv.S, bv.frame > 0, x, y,
-                           &bv.lights, bv.vis);
-  }
+  // one block per tile, in tile order: blocks are dealt to the XCDs round
+  // robin, so the views (ordered by spp) are interleaved over the XCDs
+  const int t = (int)blockIdx.x;
+  if (n_tiles > (int)gridDim.x || t >= n_tiles) return;  // more tiles than the grid: a different table
+  const BatchViewK &bv = vs[batch_find<false>(vs, n_views, t)];
+  const int local = t - bv.rs_begin;
+  const int x = (local % bv.rs_tiles_x) * 64 + (int)(threadIdx.x & 63);
+  const int y = (local / bv.rs_tiles_x) * 4 + (int)(threadIdx.x >> 6);
+  const ViewK cur = bv.cur;
+  if (x >= cur.W || y >= cur.H) return;
+  const ParamsK P = batch_params(hd->base, bv);
+  ViewK prev = cur;
+  prev.n = bv.prev_n;
+  prev.z = bv.prev_z;
+  reproject_sample_pixel(P, cur, prev, (const TG *)bv.gprev, (TG *)bv.gout, bv.S, bv.frame > 0, x, y,
+                         &bv.lights, bv.vis);
 }
 
 // Training over the TW x TH tiles of the views of class `cls`, one block per

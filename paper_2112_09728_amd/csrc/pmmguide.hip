@@ -5,10 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <map>
-#include <mutex>
 #include <string>
-#include <tuple>
 #include <type_traits>
 
 #include "pg_kernels.hpp"
@@ -175,27 +172,6 @@ pg_status pick_tile(const pg_params *p, int spp, Tile &t) {
   if (tile_lds(t, spp) > 64 * 1024)
     return fail(PG_ERR_UNSUPPORTED, "tile %dx%d with spp %d needs %zu B of LDS (> 64 KiB)", t.w, t.h, spp,
                 tile_lds(t, spp));
-  return PG_OK;
-}
-
-// Blocks of a persistent launch: every CU filled to the kernel's occupancy
-// (queried once per device, kernel and LDS size).
-pg_status persistent_blocks(const void *kernel, int threads, size_t lds, int &blocks) {
-  static std::mutex mu;
-  static std::map<std::tuple<int, const void *, size_t>, int> cache;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return fail(PG_ERR_HIP, "no current device");
-  const auto key = std::make_tuple(dev, kernel, lds);
-  std::lock_guard<std::mutex> lock(mu);
-  auto it = cache.find(key);
-  if (it == cache.end()) {
-    int cus = 0, per = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, lds) != hipSuccess)
-      return fail(PG_ERR_HIP, "device query failed: %s", hipGetErrorString(hipGetLastError()));
-    it = cache.emplace(key, cus * (per > 0 ? per : 1)).first;
-  }
-  blocks = it->second;
   return PG_OK;
 }
 
@@ -766,11 +742,10 @@ pg_status pg_frame_batched(const void *host_table, void *device_table, size_t by
     return fail(PG_ERR_HIP, "pg_frame_batched: table upload failed: %s", hipGetErrorString(hipGetLastError()));
   return dispatch_dtype(hd.dtype, [&](auto *tag) {
     using TG = std::remove_pointer_t<decltype(tag)>;
-    int blocks = 0;
-    pg_status e = persistent_blocks((const void *)k_rs_batched<TG>, 256, 0, blocks);
-    if (e) return e;
-    if (blocks > hd.rs_tiles) blocks = hd.rs_tiles;
-    hipLaunchKernelGGL((k_rs_batched<TG>), dim3(blocks), dim3(256), 0, s, (const char *)device_table, hd.dtype);
+    pg_status e;
+    if (hd.rs_tiles > 0)
+      hipLaunchKernelGGL((k_rs_batched<TG>), dim3(hd.rs_tiles), dim3(256), 0, s, (const char *)device_table,
+                         hd.dtype);
     if ((e = check_launch("pg_frame_batched (sampling)"))) return e;
     for (int c = 0; c < hd.n_classes; ++c)
       if ((e = launch_em_batched<TG>(hd.cls[c], device_table, hd.dtype, c, s))) return e;
