@@ -303,11 +303,12 @@ typedef struct pg_ceiling {
 pg_status pg_light_ceiling(const pg_ceiling *c, const pg_view *v, const float *position,
                            const pg_samples *samples, float *hit_dist, void *stream);
 
-/* ---- Batched frame: many views in two persistent launches ----------------
+/* ---- Batched frame: many views in a few launches -------------------------
  * One frame of n views of any size and spp (Sec. 3.1 and Sec. 3.2 for each
  * view, with the light-field stand-in between them) as an upload of a packed
- * table followed by two persistent launches over the tiles of all views:
- * reprojection + guided sampling + light field, then the online EM update.
+ * table followed by launches over the tiles of all views: reprojection +
+ * guided sampling + light field, then the online EM update (one launch per
+ * spp group).
  * Per view the results are bit-identical to pg_reproject_sample,
  * pg_light_field and pg_em_update called with that view's arguments and the
  * same training tile. */

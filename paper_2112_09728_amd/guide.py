@@ -107,9 +107,9 @@ class LobesGuide(Guide):
 
 
 class BatchedGuide:
-    """Many views stepped together: per frame one packed table and the two
-    persistent launches of pg_frame_batched, run eagerly or replayed from
-    captured graphs.
+    """Many views stepped together: per frame one packed table and the
+    launches of pg_frame_batched over the tiles of all views, run eagerly or
+    replayed from captured graphs.
 
     specs: one dict per view with width, height, spp, seed, lights, ambient
     (and optionally view, the view id; default its position).  Two pinned host
