@@ -48,6 +48,21 @@ def records_host(s: pg.Samples):
                 strategy=host(s.strategy), radiance=host(s.radiance))
 
 
+def paired_ratio_ci(err_a, err_b, n_boot=2000, seed=0):
+    """sum(err_a) / sum(err_b) and its 95% bootstrap interval, resampling the
+    pixels with replacement and keeping each pixel's pair of errors together
+    (both runs drew the same random numbers for a pixel, so the pairing
+    removes most of the noise the two estimates share)."""
+    a = np.asarray(err_a, np.float64).reshape(-1)
+    b = np.asarray(err_b, np.float64).reshape(-1)
+    rng = np.random.default_rng(seed)
+    r = np.empty(n_boot)
+    for i0 in range(0, n_boot, 100):
+        idx = rng.integers(0, a.size, (min(100, n_boot - i0), a.size), dtype=np.int32)
+        r[i0:i0 + idx.shape[0]] = a[idx].sum(1) / b[idx].sum(1)
+    return float(a.sum() / b.sum()), float(np.quantile(r, 0.025)), float(np.quantile(r, 0.975))
+
+
 def rel_err(a, b, floor=1e-30):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)

@@ -5,7 +5,7 @@ Parity of pg_estimate with the oracle on the same records, and the point of
 the method on the analytic light field: on the 1080p camera-pan sequence the
 1-spp estimate with guided sampling against BRDF sampling alone (pi held at
 0), relative MSE against an FP64 reference integral (mixture of BRDF and
-light-lobe sampling, 8192 samples per pixel) on 8192 random guided pixels at
+light-lobe sampling, 2048 samples per pixel) on 32768 random guided pixels at
 four frames, by roughness class."""
 import sys
 
@@ -16,7 +16,7 @@ import torch
 import oracle as O
 import paper_2112_09728_amd as pg
 from paper_2112_09728_amd import workload as wl
-from pgtest import dev, gpu_view, host, random_gamma, records_host, rel_err
+from pgtest import paired_ratio_ci, dev, gpu_view, host, random_gamma, records_host, rel_err
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
@@ -50,7 +50,7 @@ def test_estimate_parity(W, H, spp):
 def test_guided_estimator_against_brdf_sampling():
     cfg = wl.CONFIGS["1080p_spp1_64f_fp32_pan"]
     W, H, seed = 1920, 1080, cfg["seed"]
-    frames, evals, n_px, n_ref = 32, (7, 15, 23, 31), 8192, 8192
+    frames, evals, n_px, n_ref = 32, (7, 15, 23, 31), 32768, 2048
     say(f"case: estimator study, 1080p pan, frames {evals}, {n_px} px, reference {n_ref} samples")
     seq = wl.Sequence(W, H, seed)
     fr = seq.frame(0)
@@ -60,6 +60,7 @@ def test_guided_estimator_against_brdf_sampling():
     rng = np.random.default_rng(seed)
     classes = [(0.1, 0.3), (0.3, 0.6), (0.6, 1.01)]
     acc = {c: {"g": 0.0, "b": 0.0, "ref2": 0.0, "n": 0, "se2": 0.0} for c in classes}
+    pairs_g, pairs_b = [], []
     prev = None
     for t in range(frames):
         if t:
@@ -80,6 +81,8 @@ def test_guided_estimator_against_brdf_sampling():
         px = np.sort(rng.choice(cand, size=n_px, replace=False))
         ref, se = O.reference(O.params(seed, frame=t), O.OView(fr), lights, amb, fr["vis"], px, n_ref)
         r = rough.reshape(-1)[px]
+        pairs_g.append((eg.reshape(-1)[px] - ref) ** 2 / (ref ** 2).sum())
+        pairs_b.append((eb.reshape(-1)[px] - ref) ** 2 / (ref ** 2).sum())
         for c in classes:
             m = (r >= c[0]) & (r < c[1])
             a = acc[c]
@@ -100,4 +103,6 @@ def test_guided_estimator_against_brdf_sampling():
     say(f"  all | {sum(acc[c]['n'] for c in classes)} | {tot['b'] / tot['ref2']:.4f} | "
         f"{tot['g'] / tot['ref2']:.4f} | {ratio:.3f} | {tot['se2'] / tot['g']:.1e}")
     assert tot["se2"] < 0.05 * tot["g"]  # the reference is far more accurate than either estimate
+    rr, lo, hi = paired_ratio_ci(np.concatenate(pairs_g), np.concatenate(pairs_b))
+    say(f"  guided / BRDF-only MSE over the evaluated frames: {rr:.3f}, paired bootstrap 95% [{lo:.3f}, {hi:.3f}]")
     assert ratio < 1.0

@@ -16,7 +16,7 @@ import torch
 import oracle as O
 import paper_2112_09728_amd as pg
 from paper_2112_09728_amd import workload as wl
-from pgtest import (MARGIN, TOL_DIR, TOL_EM_FRAME, TOL_EM_RUN, TOL_PDF, EVIDENCE_FLOOR, assert_gamma_close,
+from pgtest import (MARGIN, paired_ratio_ci, TOL_DIR, TOL_EM_FRAME, TOL_EM_RUN, TOL_PDF, EVIDENCE_FLOOR, assert_gamma_close,
                     assert_gamma_quantile, dev, gpu_view, host, records_host, rel_err)
 
 pytestmark = [pytest.mark.gpu,
@@ -371,13 +371,13 @@ def test_1080p_pan_k2_sampled_pixels():
 def test_lobes_study_1080p_pan():
     """What more lobes buy on the 1080p pan (three spherical-Gaussian lights,
     1 spp): the relative MSE of the first-bounce estimate against the FP64
-    reference on 4096 pixels at a few frames, for K = 1 (the single-lobe
+    reference (1024 samples per pixel) on 32768 pixels at a few frames, for K = 1 (the single-lobe
     kernels), 2 and 3 (reported; the guard is that K lobes never cost more
     than 10% over one)."""
     cfg = wl.CONFIGS["1080p_spp1_64f_fp32_pan"]
     W, H, seed, frames = 1920, 1080, cfg["seed"], 24
     evals = (4, 8, 16, 23)
-    n_px, n_ref = 4096, 4096
+    n_px, n_ref = 32768, 1024
     say(f"case: lobes study, 1080p pan, {n_px} px")
     seq = wl.Sequence(W, H, seed)
     fr = seq.frame(0)
@@ -388,6 +388,7 @@ def test_lobes_study_1080p_pan():
     rng = np.random.default_rng(seed + 2)
     prev = None
     rows = []
+    errs = {k: [] for k in runs}
     for t in range(frames):
         if t:
             fr = seq.frame(t)
@@ -405,9 +406,15 @@ def test_lobes_study_1080p_pan():
         r2 = float((ref ** 2).sum())
         mse = {k: float(((e.reshape(-1)[px] - ref) ** 2).sum()) / r2 for k, e in est.items()}
         rows.append((t, mse))
+        if t != evals[0]:
+            for k, e in est.items():
+                errs[k].append((e.reshape(-1)[px] - ref) ** 2 / r2)
         say(f"  frame {t:2d}: rel. MSE " + ", ".join(f"K={k} {v:.4f}" for k, v in mse.items()))
     mean = {k: float(np.mean([r[1][k] for r in rows[1:]])) for k in runs}
     say(f"  mean rel. MSE over frames {evals[1:]}: " + ", ".join(f"K={k} {v:.4f}" for k, v in mean.items()))
+    for k in (2, 3):
+        rr, lo, hi = paired_ratio_ci(np.concatenate(errs[k]), np.concatenate(errs[1]))
+        say(f"  K = {k} / K = 1 MSE: {rr:.3f}, paired bootstrap 95% [{lo:.3f}, {hi:.3f}]")
     assert all(np.isfinite(v) for r in rows for v in r[1].values())
     assert mean[2] <= 1.1 * mean[1] and mean[3] <= 1.1 * mean[1], mean
 

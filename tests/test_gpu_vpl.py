@@ -11,7 +11,7 @@ import torch
 import oracle as O
 import paper_2112_09728_amd as pg
 from paper_2112_09728_amd import workload as wl
-from pgtest import (TOL_EM_FRAME, TOL_EM_RUN, EVIDENCE_FLOOR, assert_gamma_close, assert_gamma_quantile, dev, host,
+from pgtest import (paired_ratio_ci, TOL_EM_FRAME, TOL_EM_RUN, EVIDENCE_FLOOR, assert_gamma_close, assert_gamma_quantile, dev, host,
                     records_host, rel_err)
 
 pytestmark = [pytest.mark.gpu,
@@ -166,13 +166,13 @@ def test_vpl_study_1080p_pan_under_the_ceiling():
     """What positional reuse buys: the 1080p pan lit by the ceiling's lamps
     (1 spp, one lobe), trained with the neighbours' directions reused as they
     are (every hit distance +inf) and with positional reuse; relative MSE of
-    the first-bounce estimate against the FP64 reference (16384 BRDF draws per
-    pixel) on 4096 guided pixels at frames 8, 16 and 23 (reported; the guard is
+    the first-bounce estimate against the FP64 reference (2048 BRDF draws per
+    pixel) on 32768 guided pixels at frames 8, 16 and 23 (reported; the guard is
     that positional reuse never costs more than 10%)."""
     cfg = wl.CONFIGS["1080p_spp1_64f_fp32_pan"]
     W, H, seed, frames, K = 1920, 1080, cfg["seed"], 24, 1
     evals = (8, 16, 23)
-    n_px, n_ref = 4096, 16384
+    n_px, n_ref = 32768, 2048
     say(f"case: vpl study, 1080p pan under the ceiling, {n_px} px")
     seq = wl.Sequence(W, H, seed)
     fr = seq.frame(0)
@@ -183,6 +183,7 @@ def test_vpl_study_1080p_pan_under_the_ceiling():
     rng = np.random.default_rng(seed + 3)
     prev = None
     rows = []
+    errs = {m: [] for m in runs}
     for t in range(frames):
         if t:
             fr = seq.frame(t)
@@ -207,10 +208,14 @@ def test_vpl_study_1080p_pan_under_the_ceiling():
         r2 = float((ref ** 2).sum())
         mse = {m: float(((e.reshape(-1)[px] - ref) ** 2).sum()) / r2 for m, e in est.items()}
         rows.append(mse)
+        for m, e in est.items():
+            errs[m].append((e.reshape(-1)[px] - ref) ** 2 / r2)
         say(f"  frame {t:2d}: rel. MSE, directions reused {mse['dir']:.4f}, positions reused {mse['pos']:.4f} "
             f"(reference rel. s.e. {float(np.median(se / np.maximum(ref, 1e-30))):.4f})")
     mean = {m: float(np.mean([r[m] for r in rows])) for m in runs}
     say(f"  mean rel. MSE: directions reused {mean['dir']:.4f}, positions reused {mean['pos']:.4f}")
+    rr, lo, hi = paired_ratio_ci(np.concatenate(errs["pos"]), np.concatenate(errs["dir"]))
+    say(f"  positions / directions reused MSE: {rr:.3f}, paired bootstrap 95% [{lo:.3f}, {hi:.3f}]")
     assert all(np.isfinite(v) for r in rows for v in r.values())
     assert mean["pos"] <= 1.1 * mean["dir"], mean
 
