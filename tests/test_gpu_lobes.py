@@ -368,19 +368,20 @@ def test_1080p_pan_k2_sampled_pixels():
 
 
 # ----------------------------------------------------------------- what it is for
-def test_lobes_study_1080p_pan():
-    """What more lobes buy on the 1080p pan (three spherical-Gaussian lights,
-    1 spp): the relative MSE of the first-bounce estimate against the FP64
-    reference (1024 samples per pixel) on 32768 pixels at a few frames, for K = 1 (the single-lobe
-    kernels), 2 and 3 (reported; the guard is that K lobes never cost more
-    than 10% over one)."""
+def _lobes_study(all_visible):
     cfg = wl.CONFIGS["1080p_spp1_64f_fp32_pan"]
     W, H, seed, frames = 1920, 1080, cfg["seed"], 24
-    evals = (4, 8, 16, 23)
+    evals = (4, 8, 16, 23)  # errors compared over frames 8, 16 and 23
     n_px, n_ref = 32768, 1024
-    say(f"case: lobes study, 1080p pan, {n_px} px")
+    say(f"case: lobes study, 1080p pan, {n_px} px, {'every light visible' if all_visible else 'visibility coins'}")
     seq = wl.Sequence(W, H, seed)
-    fr = seq.frame(0)
+
+    def frame(t):
+        fr = seq.frame(t)
+        if all_visible:
+            fr["vis"] = np.full_like(fr["vis"], 7)
+        return fr
+    fr = frame(0)
     amb = float(fr["ambient"])
     runs = {1: pg.Guide(W, H, fr["lights"], amb, spp=1, seed=seed),
             2: pg.LobesGuide(W, H, fr["lights"], amb, lobes=2, spp=1, seed=seed),
@@ -391,7 +392,7 @@ def test_lobes_study_1080p_pan():
     errs = {k: [] for k in runs}
     for t in range(frames):
         if t:
-            fr = seq.frame(t)
+            fr = frame(t)
         cur = pg.DeviceFrame(fr)
         for g in runs.values():
             g.step(cur, prev, frame=t)
@@ -412,12 +413,33 @@ def test_lobes_study_1080p_pan():
         say(f"  frame {t:2d}: rel. MSE " + ", ".join(f"K={k} {v:.4f}" for k, v in mse.items()))
     mean = {k: float(np.mean([r[1][k] for r in rows[1:]])) for k in runs}
     say(f"  mean rel. MSE over frames {evals[1:]}: " + ", ".join(f"K={k} {v:.4f}" for k, v in mean.items()))
+    ci = {}
     for k in (2, 3):
-        rr, lo, hi = paired_ratio_ci(np.concatenate(errs[k]), np.concatenate(errs[1]))
-        say(f"  K = {k} / K = 1 MSE: {rr:.3f}, paired bootstrap 95% [{lo:.3f}, {hi:.3f}]")
+        ci[k] = paired_ratio_ci(np.concatenate(errs[k]), np.concatenate(errs[1]))
+        say(f"  K = {k} / K = 1 MSE: {ci[k][0]:.3f}, paired bootstrap 95% [{ci[k][1]:.3f}, {ci[k][2]:.3f}]")
     assert all(np.isfinite(v) for r in rows for v in r[1].values())
+    return mean, ci
+
+
+def test_lobes_study_1080p_pan():
+    """What more lobes buy on the 1080p pan (three spherical-Gaussian lights,
+    per-pixel visibility coins, 1 spp): the relative MSE of the first-bounce
+    estimate against the FP64 reference (1024 samples per pixel) on 32768
+    pixels at a few frames, for K = 1 (the single-lobe kernels), 2 and 3, with
+    paired bootstrap intervals (reported: no effect on this field, whose
+    neighbours see other lights than the pixel; the guard is that K lobes
+    never cost more than 10% over one)."""
+    mean, ci = _lobes_study(all_visible=False)
     assert mean[2] <= 1.1 * mean[1] and mean[3] <= 1.1 * mean[1], mean
 
+
+def test_lobes_study_every_light_visible():
+    """The same with every light visible from every pixel, so that each
+    pixel's incident radiance has up to three stable lobes (the case a single
+    Gaussian cannot fit): the MSE ratios of K = 2 and 3 against one lobe lie
+    below one (by 1.5-3%, at the edge of their paired intervals)."""
+    mean, ci = _lobes_study(all_visible=True)
+    assert ci[3][0] < 1.0 and ci[2][0] < 1.0, ci
 
 # ------------------------------------------------------------------ edge cases
 @pytest.mark.parametrize("K,W,H,spp", [(2, 1, 1, 1), (3, 70, 1, 2), (2, 1, 37, 3), (4, 45, 13, 8), (1, 33, 9, 8)])
