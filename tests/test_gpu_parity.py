@@ -399,3 +399,64 @@ def test_run_ragged_shuffle():
     say("case: run 71x43 spp1 independent motion")
     gf, of, worst = _run_parity(71, 43, 1, 6, 8200, _shuffle_frames)
     say(f"  teacher-forced worst {worst}")
+
+
+# ------------------------------------------------------- non-finite inputs
+def test_nonfinite_gbuffer_inputs():
+    """NaN and Inf sprinkled into the normals, view directions, depths,
+    roughness, albedo and motion vectors: reprojection decisions, strategy
+    codes and the update agree with the oracle pixel for pixel, and a state
+    is finite exactly where the oracle's is (an infinite normal component can
+    pass the validity test and carry a history into a frame that is not
+    finite; the next frame restarts such a model, as any non-finite
+    history)."""
+    W, H, spp, seed = 71, 43, 2, 16000
+    say("case: non-finite G-buffer inputs")
+    scene = wl.make_scene(W, H, seed)
+    rng = np.random.default_rng(seed)
+    bad = dict(scene)
+    for key in ("normal", "view_dir", "depth", "roughness", "albedo"):
+        a = np.array(scene[key], copy=True)
+        m = rng.uniform(size=a.shape[-2:]) < 0.03
+        vals = rng.choice([np.nan, np.inf, -np.inf], size=int(m.sum())).astype(np.float32)
+        if a.ndim == 3:
+            a[rng.integers(0, a.shape[0]), m] = vals
+        else:
+            a[m] = vals
+        bad[key] = a
+    mv, mask = wl.make_motion(W, H, seed, 3)
+    mm = rng.uniform(size=(H, W)) < 0.03
+    mv[0, mm] = rng.choice([np.nan, np.inf], size=int(mm.sum()))
+    g_prev = random_gamma(H, W, rng, k_lo=0)
+    p, P = _p(seed, 3)
+    cur, prev = gpu_view(bad, dev(mv), dev(mask)), gpu_view(scene)
+    go = torch.empty_like(dev(g_prev))
+    src = torch.empty((H, W), dtype=torch.int32, device="cuda")
+    pg.reproject(p, cur, prev, dev(g_prev), go, src)
+    s = pg.Samples(spp, H, W)
+    pg.sample_mis(p, cur, go, s)
+    pg.light_field(pg.lights_struct(scene["lights"], float(scene["ambient"])), cur, dev(scene["vis"]), s)
+    torch.cuda.synchronize()
+    vo = O.OView(bad, mv, mask)
+    g_o, src_o = O.reproject(P, vo, O.OView(scene), g_prev)
+    assert (host(src) == src_o).all()
+    gg = host(go)
+    fin_state = np.isfinite(g_o).all(0)
+    assert (np.isfinite(gg).all(0) == fin_state).all()
+    assert gamma_errors(gg[:, fin_state], g_o[:, fin_state])["mu"].max(initial=0) <= TOL_DIR
+    rec_g = records_host(s)
+    rec_o = O.sample(P, vo, gg, spp)
+    fin = fin_state & np.isfinite(rec_o["pdf_mix"]).all(0) & np.isfinite(rec_o["dir"]).all((0, 1))
+    near = rec_o["margin"] < MARGIN
+    assert ((rec_g["strategy"] == rec_o["strategy"]) | near | ~fin[None]).all()
+    live = ((rec_g["strategy"] == 1) | (rec_g["strategy"] == 2)) & fin[None]
+    assert np.isfinite(rec_g["dir"][:, live]).all() and np.isfinite(rec_g["pdf_mix"][live]).all()
+    gt = dev(gg)
+    pg.em_update(p, cur, s, gt)
+    torch.cuda.synchronize()
+    g_e, stats = O.em(P, vo, rec_g, gg, with_stats=True)
+    ge = host(gt)
+    ok = np.isfinite(g_e).all(0) & ~underflow_mask(stats)
+    assert np.isfinite(ge[:, ok]).all()
+    st = assert_gamma_quantile(ge, g_e, TOL_EM_FRAME, TOL_EM_RUN, mask=ok, what="non-finite inputs")
+    say(f"  non-finite states {int((~fin_state).sum())}, resets {int((src_o < 0).sum())}, EM {st}")
