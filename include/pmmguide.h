@@ -28,7 +28,10 @@
  *       0 mu_x, 1 mu_y, 2 Sigma_xx, 3 Sigma_xy, 4 Sigma_yy, 5 pi, 6 W, 7 k
  *     (k the training epoch, W the running evidence).  All arithmetic is
  *     FP32 whatever the storage type; stores round to nearest-even and W
- *     saturates at the format's largest finite value.
+ *     saturates at the format's largest finite value.  k is stored in the
+ *     state's type too, so every call given an FP16 state rejects k_max >
+ *     2048 and every call given a BF16 state k_max > 256 (PG_ERR_ARG): above
+ *     those the type no longer holds every integer up to k_max.
  *   - Strategy codes: 0 no sample (omega_o below the surface), 1 BRDF
  *     sample, 2 guided sample, 3 guided draw outside the unit square (null),
  *     4 BRDF draw below the horizon (null).  Null samples record zeros.
@@ -208,12 +211,19 @@ pg_status pg_light_field(const pg_lights *lights, const pg_view *v, const uint8_
 pg_status pg_em_update(const pg_params *p, const pg_view *v, const pg_samples *in,
                        pg_gamma gamma_inout, int32_t iterations, void *stream);
 
-/* Radiance-weighted negative log-likelihood of the mixture over each pixel's
- * EM training set and its adjoint.  theta [8][H*pitch] FP32 holds
- * (mu_x, mu_y, l11, l21, l22, logit pi, unused, k) with Sigma = L L^T; the
- * Gaussian uses Sigma + eps I.  Writes nll [H*pitch] (nullable) and, when
- * grad_theta is not NULL, grad_theta = grad_out * dNLL/dtheta ([8][H*pitch];
- * channels 6 and 7 are 0; grad_out NULL means 1). */
+/* Radiance-weighted negative log-likelihood of the mixture density D of
+ * Eq. (2) over each pixel's EM training set (Sec. 3.2: the samples and
+ * weights w = L f_r cos / p_src of pg_em_update's E-step), and its adjoint:
+ *   NLL = -sum_j w_j log(pi N(M^-1 w_j)/(2 pi) + (1 - pi) p_b(w_j)),
+ * the objective whose maximum-likelihood fit the EM update approaches, here
+ * as a function a gradient method can minimise instead.  theta [8][H*pitch]
+ * FP32 holds (mu_x, mu_y, l11, l21, l22, logit pi, unused, k) with
+ * Sigma = L L^T; the Gaussian uses Sigma + eps I and k selects the number of
+ * neighbour picks as in pg_em_update.  Writes nll [H*pitch] (nullable) and,
+ * when grad_theta is not NULL, grad_theta = grad_out * dNLL/dtheta
+ * ([8][H*pitch]; channels 6 and 7 are 0; grad_out NULL means 1).  theta and
+ * the records are caller-owned device memory; PG_ERR_ARG when theta is NULL
+ * or both outputs are NULL. */
 pg_status pg_nll_backward(const pg_params *p, const pg_view *v, const pg_samples *in,
                           const float *theta, const float *grad_out, float *grad_theta,
                           float *nll, void *stream);

@@ -11,7 +11,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# PG_ORACLE_LIB names another build of the same source (the sanitizer build
+# of the CPU test suite uses it)
+LIB_PATH = os.environ.get("PG_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 NO_CLAMP = 1
 STALE_RESET = 4

@@ -12,17 +12,24 @@ SRC = os.path.join(HERE, "oracle.c")
 OUT = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose: bool = False) -> str:
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
+
+
+def build(verbose: bool = False, out: str = OUT, sanitize: bool = False) -> str:
+    """Compile the oracle into `out`.  sanitize=True builds it with
+    AddressSanitizer and UndefinedBehaviorSanitizer (any report aborts); the
+    process that loads such a build must preload libasan and libubsan."""
     cmd = [
-        "gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+        "gcc", "-O1" if sanitize else "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
         "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unused-variable",
-        SRC, "-o", OUT + ".tmp", "-lm",
+        *(SANITIZE if sanitize else []),
+        SRC, "-o", out + ".tmp", "-lm",
     ]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(OUT + ".tmp", OUT)
-    return OUT
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

@@ -67,10 +67,22 @@ pg_status check_view(const pg_view *v, const char *name, bool need_albedo) {
   return PG_OK;
 }
 
-pg_status check_gamma(pg_gamma g, const char *name) {
+// The epoch k is stored in the state's own type, so k_max must be an integer
+// the type holds exactly together with every smaller one: 2^8 for BF16 (8
+// significant bits), 2^11 for FP16 (11); beyond that k + 1 rounds back to k
+// and the epoch would stop short of k_max.
+constexpr int kMaxEpochBF16 = 256, kMaxEpochF16 = 2048;
+
+pg_status check_gamma(const pg_params *p, pg_gamma g, const char *name) {
   if (!g.data) return fail(PG_ERR_ARG, "%s.data is NULL", name);
   if (g.dtype != PG_F32 && g.dtype != PG_F16 && g.dtype != PG_BF16)
     return fail(PG_ERR_ARG, "%s: unknown dtype %d", name, g.dtype);
+  if (g.dtype == PG_BF16 && p->k_max > kMaxEpochBF16)
+    return fail(PG_ERR_ARG, "%s: k_max %d exceeds %d, the largest epoch a BF16 state holds exactly", name, p->k_max,
+                kMaxEpochBF16);
+  if (g.dtype == PG_F16 && p->k_max > kMaxEpochF16)
+    return fail(PG_ERR_ARG, "%s: k_max %d exceeds %d, the largest epoch an FP16 state holds exactly", name, p->k_max,
+                kMaxEpochF16);
   return PG_OK;
 }
 
@@ -260,14 +272,14 @@ pg_status in_view(pg_status st, int i) {
 pg_status check_batch_view(const pg_batch_view &b, int dtype) {
   pg_status st;
   if ((st = check_params(&b.params)) || (st = check_view(&b.cur, "cur", true)) ||
-      (st = check_gamma(b.gamma_out, "gamma_out")) || (st = check_samples(&b.samples, true, true)) ||
+      (st = check_gamma(&b.params, b.gamma_out, "gamma_out")) || (st = check_samples(&b.samples, true, true)) ||
       (st = check_lights(&b.lights, b.vis)))
     return st;
   if (b.params.flags & PG_EM_BATCH) return fail(PG_ERR_UNSUPPORTED, "the batched frame runs the online update only");
   if (b.params.flags & PG_STALE_RESET) return fail(PG_ERR_UNSUPPORTED, "the batched frame has no stale-history reset");
   if (b.gamma_out.dtype != dtype) return fail(PG_ERR_ARG, "views store Gamma in different dtypes");
   if (b.params.frame > 0) {
-    if ((st = check_view(&b.prev, "prev", false)) || (st = check_gamma(b.gamma_in, "gamma_in"))) return st;
+    if ((st = check_view(&b.prev, "prev", false)) || (st = check_gamma(&b.params, b.gamma_in, "gamma_in"))) return st;
     if (b.prev.width != b.cur.width || b.prev.height != b.cur.height || b.prev.pitch != b.cur.pitch)
       return fail(PG_ERR_UNSUPPORTED, "the batched frame needs prev and cur of one size and pitch");
     if (b.gamma_in.dtype != dtype) return fail(PG_ERR_ARG, "gamma_in and gamma_out dtypes differ");
@@ -385,11 +397,11 @@ pg_status pg_params_default(pg_params *p) {
 pg_status pg_reproject(const pg_params *p, const pg_view *cur, const pg_view *prev, pg_gamma prev_gamma,
                        pg_gamma out_gamma, int32_t *src_index, void *stream) {
   pg_status st;
-  if ((st = check_params(p)) || (st = check_view(cur, "cur", false)) || (st = check_gamma(out_gamma, "out_gamma")))
+  if ((st = check_params(p)) || (st = check_view(cur, "cur", false)) || (st = check_gamma(p, out_gamma, "out_gamma")))
     return st;
   const bool has_prev = p->frame > 0;
   if (has_prev) {
-    if ((st = check_view(prev, "prev", false)) || (st = check_gamma(prev_gamma, "prev_gamma"))) return st;
+    if ((st = check_view(prev, "prev", false)) || (st = check_gamma(p, prev_gamma, "prev_gamma"))) return st;
     if (prev_gamma.dtype != out_gamma.dtype) return fail(PG_ERR_ARG, "prev_gamma and out_gamma dtypes differ");
     if (prev_gamma.data == out_gamma.data) return fail(PG_ERR_ARG, "prev_gamma aliases out_gamma");
   }
@@ -409,7 +421,7 @@ pg_status pg_reproject(const pg_params *p, const pg_view *cur, const pg_view *pr
 pg_status pg_sample_mis(const pg_params *p, const pg_view *v, pg_gamma gamma, const pg_samples *out,
                         void *stream) {
   pg_status st;
-  if ((st = check_params(p)) || (st = check_view(v, "view", false)) || (st = check_gamma(gamma, "gamma")) ||
+  if ((st = check_params(p)) || (st = check_view(v, "view", false)) || (st = check_gamma(p, gamma, "gamma")) ||
       (st = check_samples(out, true, false)))
     return st;
   const ParamsK P = to_k(p);
@@ -427,11 +439,11 @@ pg_status pg_reproject_sample(const pg_params *p, const pg_view *cur, const pg_v
                               pg_gamma out_gamma, const pg_samples *out, void *stream) {
   pg_status st;
   if ((st = check_params(p)) || (st = check_view(cur, "cur", false)) ||
-      (st = check_gamma(out_gamma, "out_gamma")) || (st = check_samples(out, true, false)))
+      (st = check_gamma(p, out_gamma, "out_gamma")) || (st = check_samples(out, true, false)))
     return st;
   const bool has_prev = p->frame > 0;
   if (has_prev) {
-    if ((st = check_view(prev, "prev", false)) || (st = check_gamma(prev_gamma, "prev_gamma"))) return st;
+    if ((st = check_view(prev, "prev", false)) || (st = check_gamma(p, prev_gamma, "prev_gamma"))) return st;
     if (prev_gamma.dtype != out_gamma.dtype) return fail(PG_ERR_ARG, "prev_gamma and out_gamma dtypes differ");
     if (prev_gamma.data == out_gamma.data) return fail(PG_ERR_ARG, "prev_gamma aliases out_gamma");
   }
@@ -452,7 +464,7 @@ pg_status pg_reproject_sample(const pg_params *p, const pg_view *cur, const pg_v
 pg_status pg_pdf(const pg_params *p, const pg_view *v, pg_gamma gamma, int32_t n_per_px, const float *dir,
                  float *pdf_mix, float *pdf_guide, float *pdf_brdf, void *stream) {
   pg_status st;
-  if ((st = check_params(p)) || (st = check_view(v, "view", false)) || (st = check_gamma(gamma, "gamma")))
+  if ((st = check_params(p)) || (st = check_view(v, "view", false)) || (st = check_gamma(p, gamma, "gamma")))
     return st;
   if (n_per_px < 1 || n_per_px > 64) return fail(PG_ERR_ARG, "n_per_px %d outside [1, 64]", n_per_px);
   if ((int64_t)v->pitch * v->height * n_per_px * 3 >= ((int64_t)1 << 31))
@@ -485,7 +497,7 @@ pg_status pg_light_field(const pg_lights *lights, const pg_view *v, const uint8_
 pg_status pg_em_update(const pg_params *p, const pg_view *v, const pg_samples *in, pg_gamma gamma_inout,
                        int32_t iterations, void *stream) {
   pg_status st;
-  if ((st = check_params(p)) || (st = check_view(v, "view", true)) || (st = check_gamma(gamma_inout, "gamma")) ||
+  if ((st = check_params(p)) || (st = check_view(v, "view", true)) || (st = check_gamma(p, gamma_inout, "gamma")) ||
       (st = check_samples(in, false, true)))
     return st;
   const int batch = (p->flags & PG_EM_BATCH) ? 1 : 0;

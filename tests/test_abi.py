@@ -288,3 +288,39 @@ def test_batch_pack_rejects_bad_batches():
     # too small a table, and no views
     assert _pack(ok, nbytes=pg.batch_table_bytes(2) - 1)[0] == pg.PG_ERR_ARG
     assert _pack([])[0] == pg.PG_ERR_ARG
+
+
+@no_device
+def test_low_precision_state_limits_the_epoch():
+    """k is stored in the state's type: BF16 holds every integer up to 256 and
+    FP16 up to 2048, so larger k_max values are rejected by every call that
+    takes such a state (pg_batch_pack included); FP32 accepts them."""
+    L = pg.lib()
+    v = _view()
+    s = _samples()
+    for dtype, limit in ((pg.PG_BF16, 256), (pg.PG_F16, 2048)):
+        g = pg.PgGamma(dtype, FAKE)
+        g2 = pg.PgGamma(dtype, FAKE + 4096)
+        for k_max, ok in ((limit, True), (limit + 1, False)):
+            P = pg.params(1, frame=1, k_max=k_max)
+            calls = [
+                (L.pg_reproject, (C.byref(P), C.byref(v), C.byref(v), g, g2, None, None)),
+                (L.pg_sample_mis, (C.byref(P), C.byref(v), g, C.byref(s), None)),
+                (L.pg_reproject_sample, (C.byref(P), C.byref(v), C.byref(v), g, g2, C.byref(s), None)),
+                (L.pg_pdf, (C.byref(P), C.byref(v), g, 1, None, None, None, None, None)),
+                (L.pg_em_update, (C.byref(P), C.byref(_view(albedo=True)), C.byref(s), g, 0, None)),
+            ]
+            for fn, args in calls:
+                st, msg = _status(fn, *args)
+                if ok:
+                    # the epoch check passes; a later check (NULL dir, zero
+                    # iterations) is what fails here
+                    assert "k_max" not in msg, (fn.__name__, msg)
+                else:
+                    assert st == pg.PG_ERR_ARG and f"k_max {k_max}" in msg, (fn.__name__, st, msg)
+        st, msg, _ = _pack([_bview(dtype=dtype, k_max=limit + 1)])
+        assert st == pg.PG_ERR_ARG and "k_max" in msg, msg
+        assert _pack([_bview(dtype=dtype, k_max=limit)])[0] == pg.PG_OK
+    P = pg.params(1, frame=1, k_max=100000)
+    st, msg = _status(L.pg_em_update, C.byref(P), C.byref(v), C.byref(s), pg.PgGamma(pg.PG_F32, FAKE), 0, None)
+    assert "k_max" not in msg
