@@ -425,7 +425,7 @@ def bench_batched(a):
             "workload": f"16 views ({px / 1e6:.1f} Mpx, {samples / 1e6:.0f} M samples per frame), "
                         f"camera-pan sequences, Gamma f16, graph-replayed batched frame",
             "views": [f"{w}x{h} spp{spp}" for (w, h, spp, _) in vs],
-            "tile": list(bg.tile),
+            "tile_per_spp": {str(k): list(v) for k, v in sorted(bg.tile.items())},
         },
         "plain_ms_per_step": round(ms_plain, 4),
         "batched_eager_ms_per_step": round(ms_eager, 4),

@@ -323,11 +323,14 @@ pg_status pg_light_ceiling(const pg_ceiling *c, const pg_view *v, const float *p
  * pg_light_field and pg_em_update called with that view's arguments and the
  * same training tile. */
 typedef struct pg_batch_view {
-  pg_params params;    /* seed, frame and view may differ between views; every
-                          other field must equal view 0's.  tile_w/tile_h of
-                          view 0 request a training tile: it is used for the
-                          views of every spp whose LDS it fits, the default
-                          tile of that spp elsewhere (0 = defaults)          */
+  pg_params params;    /* seed, frame, view, tile_w and tile_h may differ
+                          between views; every other field must equal view
+                          0's.  tile_w/tile_h request the training tile of
+                          the view's spp group (the views of one spp are
+                          trained by one launch, so they must request the
+                          same tile, else PG_ERR_ARG); a built tile whose
+                          LDS does not fit the spp falls back to the
+                          default tile of that spp (0 = default)            */
   pg_view cur;         /* this frame's G-buffer (albedo required)             */
   pg_view prev;        /* previous frame's (read when params.frame > 0; same
                           width, height and pitch as cur)                    */

@@ -43,7 +43,9 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     // one 32x32 -> 64-bit multiply (v_mad_u64_u32) gives both halves
     const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    // three-input XOR in one instruction (v_bitop3_b32, truth table 0x96)
+    const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+    const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
     c0 = n0;
     c1 = (uint32_t)p1;
     c2 = n2;
@@ -185,6 +187,7 @@ struct Pixel {
   float a2_pi;      // alpha^2 / pi
   float g1_wo_over_2wo;  // G1(wo) / (2 wo_z)
   float f0, s_d, s_d_pi;
+  float one_m_f0, one_m_sd;  // 1 - f0, 1 - s_d
 };
 
 __device__ __forceinline__ float smith_g1(V3 v, float alpha2) {
@@ -209,11 +212,11 @@ __device__ __forceinline__ void brdf_eval(const Pixel &px, V3 wi, float &f, floa
   const float R = __builtin_amdgcn_rcpf(den * den * woh_u * wq);
   const float A = px.a2_pi * hh * hh;  // D den^2
   const float pggx = 0.25f * A * h.z * wq * R;
-  pdf = fmaf(px.s_d_pi, wi.z, (1.0f - px.s_d) * pggx);
+  pdf = fmaf(px.s_d_pi, wi.z, px.one_m_sd * pggx);
   const float woh = woh_u * __builtin_amdgcn_rsqf(hh);
   const float m = 1.0f - woh;
   const float m2 = m * m;
-  const float F = fmaf(1.0f - px.f0, m2 * m2 * m, px.f0);
+  const float F = fmaf(px.one_m_f0, m2 * m2 * m, px.f0);
   f = fmaf(F * A * px.g1_wo_over_2wo, woh_u * R, px.albedo_pi);
 }
 
@@ -223,7 +226,7 @@ __device__ __forceinline__ float brdf_pdf_only(const Pixel &px, V3 wi) {
   const float den = fmaf(px.alpha2, h.z * h.z, fmaf(h.x, h.x, h.y * h.y));
   const float R = frcp(den * den * dot3(px.wo, h));
   const float pggx = 0.25f * px.a2_pi * hh * hh * h.z * R;
-  return fmaf(px.s_d_pi, wi.z, (1.0f - px.s_d) * pggx);
+  return fmaf(px.s_d_pi, wi.z, px.one_m_sd * pggx);
 }
 
 // ---------------------------------------------------------------------------

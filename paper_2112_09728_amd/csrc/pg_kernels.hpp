@@ -86,6 +86,8 @@ __device__ __forceinline__ Pixel make_pixel(const ParamsK &P, V3 n, V3 o, float 
   px.f0 = P.f0;
   px.s_d = P.s_d;
   px.s_d_pi = P.s_d * kInvPi;
+  px.one_m_f0 = 1.0f - P.f0;
+  px.one_m_sd = 1.0f - P.s_d;
   return px;
 }
 
@@ -513,17 +515,19 @@ struct EmCtx {
   Pixel px;
   Gauss G;
   float pi, one_m_pi;
+  float pi_norm;  // pi / (4 pi^2 l11 l22): the Gaussian term of D up to its exponential
 };
 
+// One training sample of a list (its staged record is never zero: lists
+// hold only BRDF-strategy records inside the image).
 __device__ __forceinline__ void em_visit(const EmCtx &c, float4 r, Accum &a) {
-  if (r.w == 0.0f) return;
   const V3 l = to_local(c.px.f, V3{r.x, r.y, r.z});
   if (l.z <= 0.0f) return;
   float ux, uy, f, pb;
   hemi2sq(l, ux, uy);
   brdf_eval(c.px, l, f, pb);
   const float w = r.w * f * l.z;
-  const float ga = c.pi * gauss_pdf_fast(c.G, ux, uy);
+  const float ga = c.pi_norm * __builtin_amdgcn_exp2f(-0.72134752044448170368f * gauss_q(c.G, ux, uy));
   const float gb = c.one_m_pi * pb;
   const float gam = ga * __builtin_amdgcn_rcpf(fmaxf(ga + gb, 1.17549435e-38f));
   a.B0 += w;
@@ -564,6 +568,35 @@ __device__ __forceinline__ int pick_entry(uint4 w4, int m, uint32_t cs, uint32_t
          (kR * SW + kR);
 }
 
+// Bytes of the pick table in dynamic LDS (after the records and the lists).
+__host__ __device__ constexpr int pick_table_bytes(int spp) { return (kCand * spp * 2 + 15) & ~15; }
+
+// Pick table of a tile shape: code c in [0, 48 spp) of a pick -> offset of
+// its candidate's staged record from the pixel's own: s SA + dy SW + dx with
+// (o, s) = (c div spp, c mod spp), the centre of the window skipped, and
+// (dx, dy) = (o mod 7 - 3, o div 7 - 3).  Built once per block, so that a
+// pick costs one LDS read instead of the integer arithmetic of pick_entry.
+template <int SA, int SW>
+__device__ __forceinline__ void build_pick_table(int16_t *tab, int spp) {
+  // c div spp = (c ceil(2^16 / spp)) >> 16, exact for c < 48 spp
+  const uint32_t inv_spp = (65536u + (uint32_t)spp - 1u) / (uint32_t)spp;
+  for (int c = (int)threadIdx.x; c < kCand * spp; c += (int)blockDim.x) {
+    const int o0 = (int)(__umul24((uint32_t)c, inv_spp) >> 16), s = c - o0 * spp;
+    const int o = o0 + (o0 >= kCand / 2 ? 1 : 0);
+    const int row = o / kSide;
+    tab[c] = (int16_t)(s * SA + (row - kR) * SW + (o - row * kSide - kR));
+  }
+}
+
+// The pick table of a training tile, at its place in dynamic LDS (called by
+// every thread before em_tile; em_tile's first barrier publishes it).
+template <int TW, int TH>
+__device__ __forceinline__ void build_em_pick_table(float4 *lds, int spp) {
+  constexpr int SW = TW + 2 * kR, SA = SW * (TH + 2 * kR), NT = TW * TH;
+  build_pick_table<SA, SW>(reinterpret_cast<int16_t *>(reinterpret_cast<uint16_t *>(lds + spp * SA) + (spp + 20) * NT),
+                           spp);
+}
+
 // Number of neighbour picks N(k) = 5 + floor(15 (kMax - k) / kMax) (Sec. 4.2).
 __device__ __forceinline__ int n_picks(const ParamsK &P, int k) {
   k = k < 0 ? 0 : (k > P.k_max ? P.k_max : k);
@@ -579,11 +612,10 @@ __device__ __forceinline__ int n_picks(const ParamsK &P, int k) {
 // branches (a rejected candidate's slot is overwritten by the next one; the
 // area has room for every candidate).  Returns the list length.
 template <int TW, int TH>
-__device__ __forceinline__ int build_list(const ParamsK &P, const float4 *lds, uint16_t *list, int col, int lx,
-                                          int ly, int npick, int spp, uint32_t pix) {
+__device__ __forceinline__ int build_list(const ParamsK &P, const float4 *lds, const int16_t *ptab, uint16_t *list,
+                                          int col, int lx, int ly, int npick, int spp, uint32_t pix) {
   constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH, NT = TW * TH;
   const uint32_t cs = (uint32_t)(kCand * spp);
-  const uint32_t inv_spp = (65536u + (uint32_t)spp - 1u) / (uint32_t)spp;
   const int own = (ly + kR) * SW + (lx + kR);
   int n = 0;
   {
@@ -603,9 +635,13 @@ __device__ __forceinline__ int build_list(const ParamsK &P, const float4 *lds, u
     float wv[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      e[j] = pick_entry<SA, SW>(w4, j, cs, inv_spp, (uint32_t)spp, own);
-      wv[j] = lds[e[j]].w;
+      // the 16-bit field j of the four words, scaled to a code in [0, 48 spp)
+      const uint32_t word = (j >> 1) == 0 ? w4.x : (j >> 1) == 1 ? w4.y : (j >> 1) == 2 ? w4.z : w4.w;
+      const uint32_t h = (j & 1) ? (word >> 16) : (word & 0xFFFFu);
+      e[j] = own + ptab[__umul24(h, cs) >> 16];
     }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) wv[j] = lds[e[j]].w;
 #pragma unroll
     for (int j = 0; j < 8; ++j)
       if (m0 + j < npick) {
@@ -754,7 +790,8 @@ __device__ __forceinline__ void em_load(const ViewK &v, const SamplesK &S, const
 // none leaves early; a block that runs several tiles synchronises between
 // them (the write-back area overlaps the records).
 // Dynamic LDS: records [spp][SH][SW] float4, then lists [spp + 20][NT]
-// uint16; the write-back reuses the area ([8][NT] float).
+// uint16, then the pick table [48 spp] int16; the write-back reuses the area
+// ([8][NT] float).
 template <typename TG, int TW, int TH, bool STALE = false>
 __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const SamplesK &S, TG *gamma,
                                         int iterations, int batch, int tx0, int ty0, int rot, float4 *lds,
@@ -766,6 +803,7 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
   const int t = threadIdx.x;
   const int x0 = tx0 + t % TW, y0 = ty0 + t / TW;
   const bool in_image = x0 < v.W && y0 < v.H;
+  int16_t *ptab = reinterpret_cast<int16_t *>(list + (S.spp + 20) * NT);
   if (t < 2 * kMaxLen) (&sh.cnt[0][0])[t] = 0;
   // plane-0 records to LDS
 #pragma unroll
@@ -793,7 +831,7 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
     int len = 0;
     if (nc > 0) {
       const int lx = pa % TW, ly = pa / TW;
-      len = build_list<TW, TH>(P, lds, list, pa, lx, ly, nc - S.spp, S.spp,
+      len = build_list<TW, TH>(P, lds, ptab, list, pa, lx, ly, nc - S.spp, S.spp,
                                (uint32_t)((ty0 + ly) * v.W + tx0 + lx));
     }
     sh.work[pa] = (uint8_t)len;
@@ -815,6 +853,7 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
       c.G = gauss_setup(g[0], g[1], g[2], g[3], g[4], P.eps);
       c.pi = g[5];
       c.one_m_pi = 1.0f - g[5];
+      c.pi_norm = g[5] * c.G.norm;
       Accum a = {0, 0, 0, 0, 0, 0, 0};
       for (int j = 0; j < len; ++j) em_visit(c, lds[list[j * NT + me]], a);
       if (!(a.B0 > 0.0f)) break;
@@ -881,6 +920,7 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(8))) voi
   __shared__ EmShared<TW * TH> sh;
   const int tile = xcd_tile(blockIdx.x, n_tiles);
   const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
+  build_em_pick_table<TW, TH>(lds, S.spp);  // before the loads: fewer live registers
   EmInput<TW, TH> R;
   em_load(v, S, gamma, tx0, ty0, R);
   em_tile<TG, TW, TH, STALE>(P, v, S, gamma, iterations, batch, tx0, ty0, (int)blockIdx.x, lds, sh, R);
@@ -1100,6 +1140,7 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TH == 2 
   const int l = t - bv.em_begin;
   const int tx0 = (l % bv.em_tiles_x) * TW, ty0 = (l / bv.em_tiles_x) * TH;
   const ParamsK P = batch_params(hd->base, bv);
+  build_em_pick_table<TW, TH>(lds, bv.S.spp);
   EmInput<TW, TH> R;
   em_load(bv.cur, bv.S, (const TG *)bv.gout, tx0, ty0, R);
   em_tile<TG, TW, TH>(P, bv.cur, bv.S, (TG *)bv.gout, 1, 0, tx0, ty0, (int)blockIdx.x, lds, sh, R);

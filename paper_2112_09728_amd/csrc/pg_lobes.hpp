@@ -485,6 +485,8 @@ __global__ __launch_bounds__(TW *TH) void k_lobes_em(ParamsK P, ViewK v, Samples
   const int plane = v.H * v.pitch;
   uint16_t *list = reinterpret_cast<uint16_t *>(lds + spp * SA);
   if (t < 2 * kMaxLen) (&sh.cnt[0][0])[t] = 0;
+  int16_t *ptab = reinterpret_cast<int16_t *>(list + (spp + 20) * NT);
+  build_pick_table<SA, SW>(ptab, spp);
   // the candidate count of this lane's pixel (0 when it is not trained)
   int ncand = 0;
   {
@@ -513,7 +515,8 @@ __global__ __launch_bounds__(TW *TH) void k_lobes_em(ParamsK P, ViewK v, Samples
     int len = 0;
     if (nc > 0) {
       const int lx = pa % TW, ly = pa / TW;
-      len = build_list<TW, TH>(P, lds, list, pa, lx, ly, nc - spp, spp, (uint32_t)((ty0 + ly) * v.W + tx0 + lx));
+      len = build_list<TW, TH>(P, lds, ptab, list, pa, lx, ly, nc - spp, spp,
+                               (uint32_t)((ty0 + ly) * v.W + tx0 + lx));
     }
     sh.work[pa] = (uint8_t)len;
     me = balance<NT>(len, pa, sh.cnt[1], sh.perm, (int)blockIdx.x + 1);

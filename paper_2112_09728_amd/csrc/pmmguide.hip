@@ -163,12 +163,12 @@ constexpr Tile kTiles[] = {{32, 8}, {16, 16}, {64, 4}, {32, 4}, {16, 8}, {64, 2}
 
 Tile default_tile(int spp) { return spp <= 4 ? Tile{32, 8} : Tile{32, 4}; }
 
-// Dynamic LDS of the training kernels: staged records [spp][h+6][w+6] float4
-// and the training lists [spp+20][w*h] uint16 (at least 8 floats per pixel,
-// which the Gamma write-back reuses).
+// Dynamic LDS of the training kernels: staged records [spp][h+6][w+6] float4,
+// the training lists [spp+20][w*h] uint16 and the pick table [48 spp] int16
+// (at least 8 floats per pixel, which the Gamma write-back reuses).
 size_t tile_lds(Tile t, int spp) {
   return (size_t)(t.w + 2 * kR) * (t.h + 2 * kR) * spp * sizeof(float4) +
-         (size_t)(spp + 20) * t.w * t.h * sizeof(uint16_t);
+         (size_t)(spp + 20) * t.w * t.h * sizeof(uint16_t) + (size_t)pick_table_bytes(spp);
 }
 
 pg_status pick_tile(const pg_params *p, int spp, Tile &t) {
@@ -261,7 +261,7 @@ bool shared_params_equal(const pg_params &a, const pg_params &b) {
   return a.k_max == b.k_max && a.radius == b.radius && a.pi_init == b.pi_init && a.pi_lo == b.pi_lo &&
          a.pi_hi == b.pi_hi && a.eps_sigma == b.eps_sigma && a.tau_depth == b.tau_depth &&
          a.tau_normal == b.tau_normal && a.rough_min == b.rough_min && a.s_diffuse == b.s_diffuse &&
-         a.f0 == b.f0 && a.flags == b.flags && a.tile_w == b.tile_w && a.tile_h == b.tile_h;
+         a.f0 == b.f0 && a.flags == b.flags;
 }
 
 pg_status in_view(pg_status st, int i) {
@@ -588,7 +588,7 @@ pg_status pg_em_update_lobes(const pg_params *p, int32_t lobes, const pg_view *v
   const int TH = in->spp > 4 ? 4 : 8;
   const int tx = (V.W + 31) / 32, ty = (V.H + TH - 1) / TH;
   const size_t lds_tile = (size_t)in->spp * (32 + 2 * kR) * (TH + 2 * kR) * sizeof(float4) +
-                          (size_t)(in->spp + 20) * 32 * TH * sizeof(uint16_t);
+                          (size_t)(in->spp + 20) * 32 * TH * sizeof(uint16_t) + (size_t)pick_table_bytes(in->spp);
   const size_t lds_wb = (size_t)(6 * lobes + 2) * 32 * TH * sizeof(float);  // write-back area
   const size_t lds = lds_tile > lds_wb ? lds_tile : lds_wb;
   return dispatch_lobes(lobes, [&](auto kc) {
@@ -618,7 +618,7 @@ pg_status pg_em_update_vpl(const pg_params *p, int32_t lobes, const pg_view *v, 
   const int TH = in->spp > 4 ? 4 : 8;
   const int tx = (V.W + 31) / 32, ty = (V.H + TH - 1) / TH;
   const size_t lds_tile = (size_t)in->spp * (32 + 2 * kR) * (TH + 2 * kR) * sizeof(float4) +
-                          (size_t)(in->spp + 20) * 32 * TH * sizeof(uint16_t);
+                          (size_t)(in->spp + 20) * 32 * TH * sizeof(uint16_t) + (size_t)pick_table_bytes(in->spp);
   const size_t lds_wb = (size_t)(6 * lobes + 2) * 32 * TH * sizeof(float);
   const size_t lds = lds_tile > lds_wb ? lds_tile : lds_wb;
   return dispatch_lobes(lobes, [&](auto kc) {
@@ -688,24 +688,32 @@ pg_status pg_batch_pack(const pg_batch_view *views, int32_t n_views, void *host_
     return fail(PG_ERR_ARG, "pg_batch_pack: table of %zu bytes, %zu needed", bytes, batch_bytes(n_views));
   const int dtype = views[0].gamma_out.dtype;
   pg_status st;
-  int per_spp[kMaxSpp + 1] = {0};
+  int per_spp[kMaxSpp + 1] = {0}, first_of[kMaxSpp + 1] = {0};
   for (int i = 0; i < n_views; ++i) {
     if ((st = in_view(check_batch_view(views[i], dtype), i))) return st;
     if (!shared_params_equal(views[i].params, views[0].params))
-      return in_view(fail(PG_ERR_ARG, "parameters other than seed, frame and view differ from view 0's"), i);
+      return in_view(fail(PG_ERR_ARG, "parameters other than seed, frame, view and tile differ from view 0's"), i);
     for (int j = 0; j < i; ++j)
       if (views[j].gamma_out.data == views[i].gamma_out.data || views[j].samples.dir == views[i].samples.dir)
         return in_view(fail(PG_ERR_ARG, "output buffers shared with view %d", j), i);
-    ++per_spp[views[i].samples.spp];
+    // the views of one spp share a training launch, so they request one tile
+    const int spp = views[i].samples.spp;
+    if (per_spp[spp] && (views[i].params.tile_w != views[first_of[spp]].params.tile_w ||
+                         views[i].params.tile_h != views[first_of[spp]].params.tile_h))
+      return in_view(fail(PG_ERR_ARG, "views of spp %d request different training tiles (view %d asks for %dx%d)",
+                          spp, first_of[spp], views[first_of[spp]].params.tile_w,
+                          views[first_of[spp]].params.tile_h), i);
+    if (!per_spp[spp]) first_of[spp] = i;
+    ++per_spp[spp];
   }
-  // classes by spp, each with its tile
+  // classes by spp, each with the tile its views request
   BatchClass cls[kMaxSpp];
   Tile ctile[kMaxSpp];
   int n_classes = 0, class_of[kMaxSpp + 1];
   for (int spp = 1; spp <= kMaxSpp; ++spp) {
     class_of[spp] = -1;
     if (!per_spp[spp]) continue;
-    if ((st = class_tile(&views[0].params, spp, ctile[n_classes]))) return st;
+    if ((st = class_tile(&views[first_of[spp]].params, spp, ctile[n_classes]))) return in_view(st, first_of[spp]);
     std::memset(&cls[n_classes], 0, sizeof(BatchClass));
     cls[n_classes].spp = spp;
     cls[n_classes].tile_w = ctile[n_classes].w;

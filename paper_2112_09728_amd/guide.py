@@ -21,6 +21,13 @@ from . import (PgBatchView, PgParams, Samples, View, _gamma, batch_pack, batch_t
 TILES = ((32, 8), (16, 16), (64, 4), (32, 4), (16, 8), (64, 2), (32, 16), (64, 8))
 
 
+def _tile_lds(tile, spp: int) -> int:
+    """Dynamic LDS bytes of a training tile (records with the 3-pixel halo,
+    the training lists and the pick table), as the library sizes it."""
+    w, h = tile
+    return (w + 6) * (h + 6) * spp * 16 + (spp + 20) * w * h * 2 + ((48 * spp * 2 + 15) & ~15)
+
+
 class DeviceFrame:
     """One frame's inputs resident on the device: the G-buffer view (with
     motion and disocclusion) and the light-visibility bits."""
@@ -115,13 +122,17 @@ class BatchedGuide:
     (and optionally view, the view id; default its position).  Two pinned host
     tables are used in turn, so packing frame t+1 only waits for the upload of
     frame t-1; each has its own captured graph.  The caller keeps the
-    DeviceFrames of the last two frames alive (the tables point at them)."""
+    DeviceFrames of the last two frames alive (the tables point at them).
+
+    tile: the training tile, one (w, h) for every spp group or a dict
+    {spp: (w, h)} (groups not named use the library's default); ``autotune``
+    picks one per group."""
 
     def __init__(self, specs, gamma_dtype=torch.float16, device="cuda", tile=None, **param_overrides):
         self.specs = [dict(s) for s in specs]
         self.n = len(self.specs)
         self.overrides = param_overrides
-        self.tile = tile
+        self.tile = dict(tile) if isinstance(tile, dict) else tile
         self.gamma = [[new_gamma(s["height"], s["width"], gamma_dtype, device),
                        new_gamma(s["height"], s["width"], gamma_dtype, device)] for s in self.specs]
         self.samples = [Samples(s["spp"], s["height"], s["width"], device) for s in self.specs]
@@ -139,10 +150,16 @@ class BatchedGuide:
     def state(self, i: int):
         return self.gamma[i][self.cur]
 
+    def tile_of(self, spp: int):
+        """The training tile requested for the views of `spp` ((0, 0): default)."""
+        if isinstance(self.tile, dict):
+            return tuple(self.tile.get(spp, (0, 0)))
+        return tuple(self.tile) if self.tile else (0, 0)
+
     def _views(self, frames, t: int):
         out = []
-        tw, th = self.tile if self.tile else (0, 0)
         for i, (s, (cur, prev)) in enumerate(zip(self.specs, frames)):
+            tw, th = self.tile_of(s["spp"])
             b = PgBatchView()
             b.params = params(s["seed"], frame=t, view=s.get("view", i), tile_w=tw, tile_h=th,
                               **self.overrides)
@@ -188,31 +205,52 @@ class BatchedGuide:
         self.cur = 1 - self.cur
         self.frame = t + 1
 
+    def _time_frame(self, frames, t: int, reps: int):
+        """ms of one batched frame with the current tiles (recomputed from the
+        same inputs, so the state is not advanced); None if a tile does not
+        fit its group."""
+        try:
+            self._pack(frames, t, self.slot)
+        except RuntimeError:
+            return None
+        self._run(self.slot, graph=False)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            frame_batched(self.host_tables[self.slot], self.dev_table)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
     def autotune(self, frames, t: int | None = None, reps: int = 3, candidates=TILES):
-        """Time the batched frame for each training tile that fits (the frame
-        is recomputed from the same inputs each time, so the state is not
-        advanced) and keep the fastest.  Returns {tile: ms}."""
+        """Pick a training tile per spp group: for each group in turn, time
+        the whole batched frame with each candidate tile for that group (the
+        other groups keep their current choice) and keep the fastest.  Only
+        the group's own launch changes between candidates, so the differences
+        are that launch's.  Returns {spp: {tile: ms}}."""
         t = self.frame if t is None else t
-        times = {}
-        saved = self.tile
-        for tile in candidates:
-            self.tile = tile
-            try:
-                self._pack(frames, t, self.slot)
-            except RuntimeError:
-                continue  # does not fit this batch's spp
-            self._run(self.slot, graph=False)
-            torch.cuda.synchronize()
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            for _ in range(reps):
-                frame_batched(self.host_tables[self.slot], self.dev_table)
-            b.record()
-            torch.cuda.synchronize()
-            times[tile] = a.elapsed_time(b) / reps
-        self.tile = min(times, key=times.get) if times else saved
-        self.graphs = [None, None]  # captured with the previous tile
-        return times
+        groups = sorted({s["spp"] for s in self.specs})
+        chosen = {spp: self.tile_of(spp) for spp in groups}
+        chosen = {spp: (tl if tl != (0, 0) else None) for spp, tl in chosen.items()}
+        out = {}
+        for spp in groups:
+            times = {}
+            for tile in candidates:
+                # a tile that does not fit this spp's LDS would fall back to
+                # the default tile: skip it
+                if _tile_lds(tile, spp) > 64 * 1024:
+                    continue
+                self.tile = {g: (tile if g == spp else chosen[g]) for g in groups if (g == spp or chosen[g])}
+                ms = self._time_frame(frames, t, reps)
+                if ms is not None:
+                    times[tile] = ms
+            if times:
+                chosen[spp] = min(times, key=times.get)
+            out[spp] = times
+        self.tile = {g: tl for g, tl in chosen.items() if tl}
+        self.graphs = [None, None]  # captured with the previous tiles
+        return out
 
 
 class NLLFunction(torch.autograd.Function):

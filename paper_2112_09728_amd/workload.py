@@ -248,6 +248,24 @@ def batched_views(n_views: int, sizes, spp_range, seed: int):
     return out
 
 
+def sequence_frames(width: int, height: int, seed: int, n_frames: int, moving: bool = True) -> list:
+    """Frames 0 .. n_frames - 1 of one camera-pan Sequence."""
+    seq = Sequence(width, height, seed, moving=moving)
+    return [seq.frame(t) for t in range(n_frames)]
+
+
+def many_sequence_frames(views, n_frames: int, workers: int = 8) -> list:
+    """sequence_frames for many views [(width, height, seed)] in worker
+    processes (spawned, so that they share nothing with a process that has
+    initialised a GPU); returns one list of frames per view, in order."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(max_workers=max(1, min(workers, len(views))),
+                                mp_context=mp.get_context("spawn")) as ex:
+        futs = [ex.submit(sequence_frames, w, h, sd, n_frames) for (w, h, sd) in views]
+        return [f.result() for f in futs]
+
+
 def crop_scene(scene: dict, x0: int, y0: int, x1: int, y1: int) -> dict:
     """A sub-rectangle of a scene as a scene of its own (same lights)."""
     out = dict(scene)

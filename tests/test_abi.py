@@ -324,3 +324,23 @@ def test_low_precision_state_limits_the_epoch():
     P = pg.params(1, frame=1, k_max=100000)
     st, msg = _status(L.pg_em_update, C.byref(P), C.byref(v), C.byref(s), pg.PgGamma(pg.PG_F32, FAKE), 0, None)
     assert "k_max" not in msg
+
+
+def test_batch_pack_tile_per_spp_group():
+    """Each spp group is trained with the tile its views request; views of
+    one spp that request different tiles are rejected."""
+    views = [_bview(w=70, h=37, spp=1, base=0, tile_w=16, tile_h=16),
+             _bview(w=70, h=37, spp=2, base=1 << 16, tile_w=64, tile_h=4),
+             _bview(w=70, h=37, spp=1, base=2 << 16, tile_w=16, tile_h=16)]
+    st, msg, table = _pack(views)
+    assert st == pg.PG_OK, msg
+    hdr = table[:32].view(torch.int32).tolist()
+    assert hdr[4] == 2  # two groups
+    # BatchClass entries follow the header and ParamsK: find them by their spp
+    ints = table.view(torch.int32).tolist()
+    groups = [ints[i:i + 3] for i in range(8, 200) if ints[i] in (1, 2) and ints[i + 1] in (16, 64)
+              and ints[i + 2] in (16, 4)]
+    assert [1, 16, 16] in groups and [2, 64, 4] in groups, groups
+    bad = [_bview(spp=1, base=0, tile_w=16, tile_h=16), _bview(spp=1, base=1 << 16, tile_w=32, tile_h=8)]
+    st, msg, _ = _pack(bad)
+    assert st == pg.PG_ERR_ARG and "different training tiles" in msg and "view 1" in msg, msg

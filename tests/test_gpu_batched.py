@@ -137,8 +137,13 @@ def test_batched_tiles_and_autotuner():
     torch.cuda.synchronize()
     before = [host(bg.state(i)) for i in range(len(sizes))]
     times = bg.autotune(frames1, 1, reps=2)
-    say("  autotuner (ms): " + ", ".join(f"{w}x{h} {ms:.3f}" for (w, h), ms in times.items()))
-    assert bg.tile in times and set(times) == set(fitted)
+    for spp, tt in times.items():
+        say(f"  autotuner spp {spp} (ms): " + ", ".join(f"{w}x{h} {ms:.3f}" for (w, h), ms in tt.items()))
+    assert set(times) == {spp for (_, _, spp) in sizes}
+    for spp, tt in times.items():
+        # every built tile whose LDS fits the group was timed; the fastest is kept
+        assert set(tt) == {tl for tl in pg.guide.TILES if pg.guide._tile_lds(tl, spp) <= 64 * 1024}
+        assert bg.tile_of(spp) == min(tt, key=tt.get)
     after = [host(bg.state(i)) for i in range(len(sizes))]
     for a, b in zip(before, after):
         assert np.array_equal(a.view(np.int32), b.view(np.int32))

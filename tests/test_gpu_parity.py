@@ -262,12 +262,34 @@ def test_em_tile_shapes_bitwise_identical(spp):
         assert (o.view(np.uint32) == outs[0].view(np.uint32)).all()
 
 
+def _amplification(P, ov, rec, g, iters, delta=1e-6):
+    """Per pixel, how much the oracle's own iters-step batch-EM map amplifies
+    a change of the starting state: max over a shift of mu_x, mu_y or pi by
+    delta of (change of the final state, in the error metric) / delta."""
+    base = O.em(P, ov, rec, g, iterations=iters, batch=True)
+    amp = np.zeros(g.shape[1:])
+    for ch in (0, 1, 5):
+        gp = np.asarray(g, np.float64).copy()
+        gp[ch] += delta
+        e = gamma_errors(O.em(P, ov, rec, gp, iterations=iters, batch=True), base)
+        for key in ("mu", "sigma", "pi"):
+            amp = np.maximum(amp, e[key] / delta)
+    return amp
+
+
 @pytest.mark.parametrize("iters", [1, 4, 16])
 @pytest.mark.parametrize("start", ["new", "random"])
 def test_batch_em_parity(iters, start):
     """Batch EM on a fixed training set.  "new" starts from the state every
     model starts from (the gradient-fit workload's start); "random" from
-    random lobes, where iterating EM can amplify rounding at a few pixels."""
+    random lobes.  Each iteration is checked teacher-forced (the oracle steps
+    from the GPU's state after the previous iteration) to the one-frame
+    tolerance.  Free-running, the FP32 rounding of the steps is carried by the
+    EM map itself, which at pixels whose lobe is still moving several
+    iterations in (a random start far from the samples) amplifies a change of
+    its input by 100x and more; there the free-running error is held to the
+    teacher-forced errors of the steps times the oracle's own measured
+    amplification of that pixel, elsewhere to the run tolerance."""
     say(f"case: batch em {iters} from {start}")
     W, H, seed = 40, 36, 6100 + iters
     scene = wl.make_scene(W, H, seed)
@@ -277,25 +299,44 @@ def test_batch_em_parity(iters, start):
     g[7] = 0
     p, P = _p(seed, 0, flags=pg.PG_EM_BATCH)
     view = gpu_view(scene)
+    ov = O.OView(scene)
     s = _gpu_records(scene, g, p, 4, view)
-    gt = dev(g)
-    pg.em_update(p, view, s, gt, iterations=iters)
-    torch.cuda.synchronize()
-    g_o, stats = O.em(P, O.OView(scene), records_host(s), g, iterations=iters, batch=True,
-                      with_stats=True)
+    rec = records_host(s)
+    # the GPU's state after every iteration (batch EM from the same start
+    # and training set is deterministic)
+    states = [g.astype(np.float32)]
+    for i in range(1, iters + 1):
+        gt = dev(g)
+        pg.em_update(p, view, s, gt, iterations=i)
+        torch.cuda.synchronize()
+        states.append(host(gt))
+    g_o, stats = O.em(P, ov, rec, g, iterations=iters, batch=True, with_stats=True)
     uf = underflow_mask(stats)
-    e = gamma_errors(host(gt), g_o)
-    for key in ("mu", "sigma", "pi"):
-        v = e[key][~uf]
-        say(f"  {key}: q0.99 {np.quantile(v, 0.99):.2e} q0.999 {np.quantile(v, 0.999):.2e} "
-            f"max {v.max():.2e} n>1e-4 {(v > 1e-4).sum()}")
-    if start == "new":
+    # teacher-forced: one oracle iteration from each GPU state
+    step_err = np.zeros((iters,) + g.shape[1:])
+    for i in range(1, iters + 1):
+        o = O.em(P, ov, rec, states[i - 1], iterations=1, batch=True)
+        e = gamma_errors(states[i], o)
+        step_err[i - 1] = np.maximum(np.maximum(e["mu"], e["sigma"]), e["pi"])
+        assert (e["k"] == 0).all()
+    tf = step_err[:, ~uf]
+    say(f"  teacher-forced per iteration: max {tf.max():.2e}, q0.999 {np.quantile(tf, 0.999):.2e}")
+    assert tf.max() <= TOL_EM_FRAME, f"batch em {iters}: a teacher-forced iteration is off by {tf.max():.2e}"
+    e = gamma_errors(states[-1], g_o)
+    free = np.maximum(np.maximum(e["mu"], e["sigma"]), e["pi"])
+    if start == "new" or iters == 1:
         tol = TOL_EM_FRAME if iters == 1 else TOL_EM_RUN
-        assert_gamma_close(host(gt), g_o, tol, mask=~uf, what=f"batch em {iters}", g_in=g)
+        assert_gamma_close(states[-1], g_o, tol, mask=~uf, what=f"batch em {iters}", g_in=g)
     else:
-        bulk = TOL_EM_FRAME if iters == 1 else TOL_EM_RUN
-        assert_gamma_quantile(host(gt), g_o, bulk, 10 * TOL_EM_RUN, mask=~uf,
-                              what=f"batch em {iters}")
+        amp = _amplification(P, ov, rec, g, iters)
+        bound = np.maximum(TOL_EM_RUN, 2.0 * np.maximum(amp, 1.0) * step_err.sum(0))
+        over = (free > bound) & ~uf
+        need = (free > TOL_EM_RUN) & ~uf
+        say(f"  free-running: max {free[~uf].max():.2e}; {int(need.sum())} pixel(s) above {TOL_EM_RUN:.0e}, "
+            f"their amplification {np.round(amp[need], 1).tolist()}")
+        assert not over.any(), (f"batch em {iters}: free-running error beyond the amplified step errors at "
+                                f"{np.argwhere(over)[:3].tolist()}: {free[over][:3]} > {bound[over][:3]}")
+        assert (e["k"][~uf] == 0).all()
 
 
 # -------------------------------------------------------------------- fused
