@@ -195,10 +195,15 @@ def main():
             ev[3].record()
         guide.cur = 1 - guide.cur
 
-    # frame 0 once untimed (first launches load the code objects); then the
-    # warm-up frames from frame 0, whose first frame (every model new, k = 0,
-    # N(0) = 20 picks) is timed on its own
-    frame(0)
+    # untimed pre-roll over every resident frame (the first launches load the
+    # code objects, every frame's inputs are touched once), then the sequence
+    # again from a new state: the warm-up frames from frame 0, whose first
+    # frame (every model new, k = 0, N(0) = 20 picks) is timed on its own,
+    # then the timed frames
+    for t in range(frames):
+        frame(t)
+    torch.cuda.synchronize()
+    reset_state(guide)
     ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     for t in range(a.warmup):
         frame(t, ev0 if t == 0 else None)
@@ -335,6 +340,13 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def reset_state(guide):
+    """A new state for every pixel (all zero; frame 0 resets every model)."""
+    for g in guide.gamma:
+        g.zero_()
+    guide.cur = 0
+
+
 def bench_batched(a):
     """16 views of uneven size and spp, FP16 Gamma: Mpix/s over all views of
     the batched frame (eager, and replayed from captured graphs) against 16
@@ -450,23 +462,48 @@ def bench_extras(a, pg, torch, dev_frames, lights, ambient, seed, W, H, S, K, fr
     1 GiB device-to-device copy."""
     out = {}
     frames = a.warmup + a.steps
-    # (1) cache-cold: replay the sequence from frame 0 on a fresh state
+
+    def replay(between):
+        """The same frames from a new state, with `between` enqueued before
+        every frame (untimed); per-kernel event times of the timed frames."""
+        reset_state(guide)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(a.steps)]
+        for t in range(frames):
+            between()
+            frame(t, evs[t - a.warmup] if t >= a.warmup else None)
+        torch.cuda.synchronize()
+        rs = np.array([e[0].elapsed_time(e[1]) for e in evs])
+        em = np.array([e[2].elapsed_time(e[3]) for e in evs])
+        ms = float((rs + em).mean())
+        return {"reproject_sample_us": round(float(rs.mean()) * 1e3, 2), "em_us": round(float(em.mean()) * 1e3, 2),
+                "ms_per_step": round(ms, 5), "mpix_s": round(W * H / (ms * 1e-3) / 1e6, 2)}
+
+    # (1) cache-cold: a clean 1 GiB read before each frame evicts the
+    # Infinity Cache; (1b) the same pause with the cache left warm (a spin of
+    # the read's duration on one wave): the two differ by the cache alone,
+    # and both differ from the back-to-back headline by the pause, during
+    # which the chip runs cooler and clocks higher for the next kernels
     scratch = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
-    for g in guide.gamma:
-        g.zero_()
-    guide.cur = 0
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(a.steps)]
     scratch.fill_(1.0)
-    for t in range(frames):
-        scratch.sum()
-        frame(t, evs[t - a.warmup] if t >= a.warmup else None)
     torch.cuda.synchronize()
-    rs = np.array([e[0].elapsed_time(e[1]) for e in evs])
-    em = np.array([e[2].elapsed_time(e[3]) for e in evs])
-    ms = float((rs + em).mean())
-    out["cache_cold"] = {"reproject_sample_us": round(float(rs.mean()) * 1e3, 2), "em_us": round(float(em.mean()) * 1e3, 2),
-                         "ms_per_step": round(ms, 5), "mpix_s": round(W * H / (ms * 1e-3) / 1e6, 2)}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        scratch.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    read_ms = e0.elapsed_time(e1) / 5
+    out["cache_cold"] = replay(lambda: scratch.sum())
+    out["cache_cold"]["pause_us"] = round(read_ms * 1e3, 1)
     del scratch
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record()
+    torch.cuda._sleep(1_000_000)
+    s1.record()
+    torch.cuda.synchronize()
+    cycles = int(1_000_000 * read_ms / s0.elapsed_time(s1))
+    out["idle_pause_warm_cache"] = replay(lambda: torch.cuda._sleep(cycles))
+    out["idle_pause_warm_cache"]["pause_us"] = round(read_ms * 1e3, 1)
     # (2) graph replay of the one-view batched frame (single-lobe FP32 path only)
     if K == 1 and not a.vpl and a.gamma_dtype == "f32" and not a.unfused:
         bg = pg.BatchedGuide([dict(width=W, height=H, spp=S, seed=seed, lights=lights, ambient=ambient, view=0)],

@@ -249,3 +249,27 @@ class GpuFrames:
 def oracle_reproject_from(P, scene, mv, mask, gamma_prev):
     v = O.OView(scene, mv, mask)
     return O.reproject(P, v, O.OView(scene), gamma_prev)
+
+
+# ------------------------------------------------------- storage formats
+FMT = {"f16": (torch.float16, 65504.0, 10), "bf16": (torch.bfloat16, 3.38953139e38, 7)}
+
+
+def round_storage(g, fmt):
+    """Round a state to the storage format (nearest even; W saturates)."""
+    g = np.asarray(g, np.float64).copy()
+    _, vmax, _ = FMT[fmt]
+    g[6] = np.minimum(g[6], vmax)
+    if fmt == "f16":
+        return g.astype(np.float16).astype(np.float64)
+    f = g.astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def ulp(v, fmt):
+    """One unit in the last place of the format at |v| (subnormal floor)."""
+    _, _, mant = FMT[fmt]
+    v = np.maximum(np.abs(np.asarray(v, np.float64)), 2.0 ** -14 if fmt == "f16" else 2.0 ** -126)
+    return 2.0 ** (np.floor(np.log2(v)) - mant)

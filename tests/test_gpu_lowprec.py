@@ -15,37 +15,15 @@ import torch
 import oracle as O
 import paper_2112_09728_amd as pg
 from paper_2112_09728_amd import workload as wl
-from pgtest import (GpuFrames, compare_samples, gamma_errors, host, rel_err, TOL_DIR,
-                    underflow_mask)
+from pgtest import (FMT, GpuFrames, compare_samples, gamma_errors, host, rel_err, round_storage, TOL_DIR,
+                    ulp, underflow_mask)
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
 
-FMT = {"f16": (torch.float16, 65504.0, 10), "bf16": (torch.bfloat16, 3.38953139e38, 7)}
-
 
 def say(*a):
     print(*a, file=sys.stderr, flush=True)
-
-
-def round_storage(g, fmt):
-    """Round a state to the storage format (nearest even; W saturates)."""
-    g = np.asarray(g, np.float64).copy()
-    _, vmax, _ = FMT[fmt]
-    g[6] = np.minimum(g[6], vmax)
-    if fmt == "f16":
-        return g.astype(np.float16).astype(np.float64)
-    f = g.astype(np.float32)
-    u = f.view(np.uint32).astype(np.uint64)
-    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
-    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
-
-
-def ulp(v, fmt):
-    """One unit in the last place of the format at |v| (subnormal floor)."""
-    _, _, mant = FMT[fmt]
-    v = np.maximum(np.abs(np.asarray(v, np.float64)), 2.0 ** -14 if fmt == "f16" else 2.0 ** -126)
-    return 2.0 ** (np.floor(np.log2(v)) - mant)
 
 
 @pytest.mark.parametrize("fmt", ["f16", "bf16"])
