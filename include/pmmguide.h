@@ -368,6 +368,23 @@ pg_status pg_batch_pack(const pg_batch_view *views, int32_t n_views, void *host_
  * output buffers. */
 pg_status pg_frame_batched(const void *host_table, void *device_table, size_t bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * pg_frame_batched with the device copy of the table held in the library's
+ * own fixed array of PG_NOALLOC_TABLE_BYTES bytes (one per GPU, kept until
+ * the process ends) instead of a caller-owned device_table.  The call itself
+ * allocates nothing: it copies host_table (pinned, as for pg_frame_batched)
+ * into that array on `stream` and launches the same kernels, so its results
+ * are those of pg_frame_batched bit for bit.  A table of more than
+ * PG_NOALLOC_TABLE_BYTES bytes (pg_batch_table_bytes) returns
+ * PG_ERR_UNSUPPORTED before any work.  Every call on one GPU uses the same
+ * array and leaves its table there: calls that overlap on one GPU (on
+ * different streams, or a replayed graph beside another call) race on it and
+ * must be ordered by the caller.  The first call on a device looks the
+ * array's address up (hipGetSymbolAddress) with that device current. */
+#define PG_NOALLOC_TABLE_BYTES 65536
+pg_status pg_frame_batched_noalloc(const void *host_table, size_t bytes, void *stream);
+
 /* Diagnostic: Philox4x32-10 (Salmon et al., SC 2011), the generator behind
  * every random draw above, for n counters: counters [n][4] uint32 and out
  * [n][4] uint32 are device arrays, key = (seed low word, seed high word). */

@@ -71,7 +71,7 @@ class PgBatchView(C.Structure):
 
 EXPORTS = ("pg_params_default", "pg_reproject", "pg_sample_mis", "pg_reproject_sample", "pg_pdf",
            "pg_light_field", "pg_em_update", "pg_nll_backward", "pg_estimate", "pg_batch_table_bytes",
-           "pg_batch_pack", "pg_frame_batched", "pg_reproject_sample_lobes", "pg_em_update_lobes",
+           "pg_batch_pack", "pg_frame_batched", "pg_frame_batched_noalloc", "pg_reproject_sample_lobes", "pg_em_update_lobes",
            "pg_pdf_lobes", "pg_em_update_vpl", "pg_light_ceiling", "pg_philox", "pg_last_error")
 MAX_LOBES = 4
 
@@ -103,6 +103,7 @@ def lib():
         L.pg_batch_table_bytes.argtypes = [C.c_int32]
         L.pg_batch_pack.argtypes = [P, C.c_int32, P, C.c_size_t]
         L.pg_frame_batched.argtypes = [P, P, C.c_size_t, P]
+        L.pg_frame_batched_noalloc.argtypes = [P, C.c_size_t, P]
         L.pg_reproject_sample_lobes.argtypes = [P, C.c_int32, P, P, P, P, P, P]
         L.pg_em_update_lobes.argtypes = [P, C.c_int32, P, P, P, P]
         L.pg_pdf_lobes.argtypes = [P, C.c_int32, P, P, C.c_int32, P, P, P]
@@ -340,6 +341,19 @@ def frame_batched(host_table, device_table) -> None:
             device_table.numel() * device_table.element_size())
     _check(lib().pg_frame_batched(C.c_void_p(host_table.data_ptr()), _ptr(device_table), n,
                                   _stream()), "pg_frame_batched")
+
+
+NOALLOC_TABLE_BYTES = 65536  # PG_NOALLOC_TABLE_BYTES
+
+
+def frame_batched_noalloc(host_table) -> None:
+    """pg_frame_batched with the device table in the library's own array (no
+    device buffer from the caller; calls on one GPU must not overlap)."""
+    if host_table.is_cuda or not host_table.is_contiguous():
+        raise ValueError("host_table must be a contiguous host tensor")
+    _check(lib().pg_frame_batched_noalloc(C.c_void_p(host_table.data_ptr()),
+                                          host_table.numel() * host_table.element_size(), _stream()),
+           "pg_frame_batched_noalloc")
 
 
 # ------------------------------------------------- K Gaussian lobes per pixel

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 
@@ -255,6 +256,38 @@ pg_status check_lights(const pg_lights *l, const uint8_t *vis) {
 constexpr int kBatchMagic = 0x31424750;  // "PGB1"
 
 size_t batch_bytes(int n) { return (size_t)kBatchViewsOffset + (size_t)n * sizeof(BatchViewK); }
+
+// Device copy of the packed table for pg_frame_batched_noalloc: a fixed
+// array in the library's own device memory (one per GPU, for the life of the
+// process).  Host code never passes the array's name to a kernel or a copy:
+// it holds the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchTableBytes = PG_NOALLOC_TABLE_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchTableBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The address of `scratch` on the current device, looked up once per device.
+pg_status scratch_table(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(PG_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PG_ERR_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(PG_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PG_OK;
+}
+
+// Upload of a packed table to device_table, then the batched launches.
+pg_status frame_batched(const void *host_table, void *device_table, size_t bytes, hipStream_t s);
 
 // Parameters every view of a batch must share (all but seed, frame, view).
 bool shared_params_equal(const pg_params &a, const pg_params &b) {
@@ -752,12 +785,33 @@ pg_status pg_batch_pack(const pg_batch_view *views, int32_t n_views, void *host_
 
 pg_status pg_frame_batched(const void *host_table, void *device_table, size_t bytes, void *stream) {
   if (!host_table || !device_table) return fail(PG_ERR_ARG, "pg_frame_batched: NULL table");
+  return frame_batched(host_table, device_table, bytes, (hipStream_t)stream);
+}
+
+pg_status pg_frame_batched_noalloc(const void *host_table, size_t bytes, void *stream) {
+  if (!host_table) return fail(PG_ERR_ARG, "pg_frame_batched_noalloc: NULL table");
+  if (bytes >= (size_t)kBatchViewsOffset) {
+    const BatchHeader *hd = reinterpret_cast<const BatchHeader *>(host_table);
+    if (hd->magic == kBatchMagic && hd->n_views >= 1 && batch_bytes(hd->n_views) > kScratchTableBytes)
+      return fail(PG_ERR_UNSUPPORTED, "pg_frame_batched_noalloc: a table of %d views needs %zu bytes, more than the %zu "
+                  "of the library's table", hd->n_views, batch_bytes(hd->n_views), kScratchTableBytes);
+  }
+  void *table = nullptr;
+  pg_status st = scratch_table(&table);
+  if (st) return st;
+  return frame_batched(host_table, table, bytes, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+pg_status frame_batched(const void *host_table, void *device_table, size_t bytes, hipStream_t s) {
   if (bytes < (size_t)kBatchViewsOffset) return fail(PG_ERR_ARG, "pg_frame_batched: table too small");
   const BatchHeader hd = *reinterpret_cast<const BatchHeader *>(host_table);
   if (hd.magic != kBatchMagic || hd.n_views < 1 || bytes < batch_bytes(hd.n_views) || hd.n_classes < 1 ||
       hd.n_classes > kMaxSpp)
     return fail(PG_ERR_ARG, "pg_frame_batched: host_table was not packed by pg_batch_pack for %zu bytes", bytes);
-  hipStream_t s = (hipStream_t)stream;
   if (hipMemcpyAsync(device_table, host_table, batch_bytes(hd.n_views), hipMemcpyHostToDevice, s) != hipSuccess)
     return fail(PG_ERR_HIP, "pg_frame_batched: table upload failed: %s", hipGetErrorString(hipGetLastError()));
   return dispatch_dtype(hd.dtype, [&](auto *tag) {
@@ -772,6 +826,10 @@ pg_status pg_frame_batched(const void *host_table, void *device_table, size_t by
     return check_launch("pg_frame_batched (training)");
   });
 }
+
+}  // namespace
+
+extern "C" {
 
 /* Diagnostic: Philox4x32-10 words for n counters (device arrays [n][4]). */
 pg_status pg_philox(int32_t n, const uint32_t *counters, uint64_t seed, uint32_t *out, void *stream) {

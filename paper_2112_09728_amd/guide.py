@@ -15,7 +15,7 @@ from __future__ import annotations
 import torch
 
 from . import (PgBatchView, PgParams, Samples, View, _gamma, batch_pack, batch_table_bytes, em_update,
-               em_update_lobes, frame_batched, light_field, lights_struct, new_gamma, new_lobes_gamma, params,
+               em_update_lobes, frame_batched, frame_batched_noalloc, light_field, lights_struct, new_gamma, new_lobes_gamma, params,
                reproject, reproject_sample, reproject_sample_lobes, sample_mis, nll_backward)
 
 TILES = ((32, 8), (16, 16), (64, 4), (32, 4), (16, 8), (64, 2), (32, 16), (64, 8))
@@ -128,18 +128,20 @@ class BatchedGuide:
     {spp: (w, h)} (groups not named use the library's default); ``autotune``
     picks one per group."""
 
-    def __init__(self, specs, gamma_dtype=torch.float16, device="cuda", tile=None, **param_overrides):
+    def __init__(self, specs, gamma_dtype=torch.float16, device="cuda", tile=None, noalloc=False,
+                 **param_overrides):
         self.specs = [dict(s) for s in specs]
         self.n = len(self.specs)
         self.overrides = param_overrides
         self.tile = dict(tile) if isinstance(tile, dict) else tile
+        self.noalloc = noalloc  # the device table in the library's own array
         self.gamma = [[new_gamma(s["height"], s["width"], gamma_dtype, device),
                        new_gamma(s["height"], s["width"], gamma_dtype, device)] for s in self.specs]
         self.samples = [Samples(s["spp"], s["height"], s["width"], device) for s in self.specs]
         self.lights = [lights_struct(s["lights"], s["ambient"]) for s in self.specs]
         nbytes = batch_table_bytes(self.n)
         self.host_tables = [torch.empty(nbytes, dtype=torch.uint8, pin_memory=True) for _ in range(2)]
-        self.dev_table = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.dev_table = None if noalloc else torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.graphs = [None, None]
         self.done = [None, None]
         self.keep = [None, None]
@@ -180,16 +182,22 @@ class BatchedGuide:
         batch_pack(self._views(frames, t), self.host_tables[slot])
         self.keep[slot] = frames
 
+    def _launch(self, slot: int):
+        if self.noalloc:
+            frame_batched_noalloc(self.host_tables[slot])
+        else:
+            frame_batched(self.host_tables[slot], self.dev_table)
+
     def _run(self, slot: int, graph: bool):
         if graph:
             if self.graphs[slot] is None:
                 g = torch.cuda.CUDAGraph()
                 with torch.cuda.graph(g, capture_error_mode="thread_local"):
-                    frame_batched(self.host_tables[slot], self.dev_table)
+                    self._launch(slot)
                 self.graphs[slot] = g
             self.graphs[slot].replay()
         else:
-            frame_batched(self.host_tables[slot], self.dev_table)
+            self._launch(slot)
         ev = torch.cuda.Event()
         ev.record()
         self.done[slot] = ev
@@ -218,7 +226,7 @@ class BatchedGuide:
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
         for _ in range(reps):
-            frame_batched(self.host_tables[self.slot], self.dev_table)
+            self._launch(self.slot)
         b.record()
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps
