@@ -28,7 +28,10 @@
  *       0 mu_x, 1 mu_y, 2 Sigma_xx, 3 Sigma_xy, 4 Sigma_yy, 5 pi, 6 W, 7 k
  *     (k the training epoch, W the running evidence).  All arithmetic is
  *     FP32 whatever the storage type; stores round to nearest-even and W
- *     saturates at the format's largest finite value.  k is stored in the
+ *     saturates at the format's largest finite value.  FP16 and BF16
+ *     states hold mu_x - 1/2 and mu_y - 1/2 in planes 0 and 1 (the means
+ *     cluster near the centre of the square, where values near zero keep
+ *     more significant bits); FP32 states hold mu.  k is stored in the
  *     state's type too, so every call given an FP16 state rejects k_max >
  *     2048 and every call given a BF16 state k_max > 256 (PG_ERR_ARG): above
  *     those the type no longer holds every integer up to k_max.

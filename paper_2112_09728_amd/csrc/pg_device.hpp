@@ -301,19 +301,34 @@ template <> struct GammaIO<bf16s> {
   static constexpr float kMax = 3.38953139e38f;
 };
 
+// FP16 and BF16 states hold mu - 1/2 in planes 0 and 1: the lobe means lie in
+// [0, 1], mostly near the centre of the square (the normal direction), where
+// a value near zero keeps more significant bits than one near 1/2; FP32
+// states hold mu itself.
+template <typename T> struct MuOffset { static constexpr float v = 0.5f; };
+template <> struct MuOffset<float> { static constexpr float v = 0.0f; };
+
+// Channel c of a state as stored (the offset taken off mu, W saturated).
+template <typename T>
+__device__ __forceinline__ void gamma_put(T *p, int c, float v) {
+  if (c < 2) v -= MuOffset<T>::v;
+  if (c == 6) v = fminf(v, GammaIO<T>::kMax);
+  GammaIO<T>::store(p, v);
+}
+template <typename T>
+__device__ __forceinline__ float gamma_get(const T *p, int c) {
+  return GammaIO<T>::load(p) + (c < 2 ? MuOffset<T>::v : 0.0f);
+}
+
 template <typename T>
 __device__ __forceinline__ void gamma_load(const T *g, int plane, int idx, float out[8]) {
 #pragma unroll
-  for (int c = 0; c < 8; ++c) out[c] = GammaIO<T>::load(g + c * plane + idx);
+  for (int c = 0; c < 8; ++c) out[c] = gamma_get(g + c * plane + idx, c);
 }
 template <typename T>
 __device__ __forceinline__ void gamma_store(T *g, int plane, int idx, const float in[8]) {
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    float v = in[c];
-    if (c == 6) v = fminf(v, GammaIO<T>::kMax);
-    GammaIO<T>::store(g + c * plane + idx, v);
-  }
+  for (int c = 0; c < 8; ++c) gamma_put(g + c * plane + idx, c, in[c]);
 }
 
 }  // namespace pgk

@@ -362,8 +362,8 @@ __device__ __forceinline__ void reproject_sample_pixel(const ParamsK &P, const V
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     TG t;
-    GammaIO<TG>::store(&t, c == 6 ? fminf(g[c], GammaIO<TG>::kMax) : g[c]);
-    gs[c] = GammaIO<TG>::load(&t);
+    gamma_put(&t, c, g[c]);
+    gs[c] = gamma_get(&t, c);
   }
   sample_pixel(P, cur, S, x, y, pi, gs, Lt, visbits);
   gamma_store(gout, cur.H * cur.pitch, idx, g);

@@ -238,12 +238,18 @@ class GpuFrames:
     def step(self, t, fr, keep=True):
         cur = pg.DeviceFrame(fr)
         g_prev = self.g.state.clone() if keep else None
+        if keep:
+            # the reprojected state this frame samples and trains with
+            g_reproj = torch.empty_like(g_prev)
+            pg.reproject(self.g.params(t), cur.view, self.prev.view if (self.prev is not None and t) else None,
+                         g_prev if t else None, g_reproj)
         out = self.g.step(cur, self.prev, frame=t)
         self.prev = cur
         torch.cuda.synchronize()
         if not keep:
             return None
-        return dict(gamma_prev=host(g_prev), gamma=host(out), rec=records_host(self.g.samples))
+        return dict(gamma_prev=host_gamma(g_prev), gamma_reproj=host_gamma(g_reproj), gamma=host_gamma(out),
+                    rec=records_host(self.g.samples))
 
 
 def oracle_reproject_from(P, scene, mv, mask, gamma_prev):
@@ -255,11 +261,7 @@ def oracle_reproject_from(P, scene, mv, mask, gamma_prev):
 FMT = {"f16": (torch.float16, 65504.0, 10), "bf16": (torch.bfloat16, 3.38953139e38, 7)}
 
 
-def round_storage(g, fmt):
-    """Round a state to the storage format (nearest even; W saturates)."""
-    g = np.asarray(g, np.float64).copy()
-    _, vmax, _ = FMT[fmt]
-    g[6] = np.minimum(g[6], vmax)
+def _round_format(g, fmt):
     if fmt == "f16":
         return g.astype(np.float16).astype(np.float64)
     f = g.astype(np.float32)
@@ -268,8 +270,38 @@ def round_storage(g, fmt):
     return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
 
 
+def round_storage(g, fmt):
+    """Round a state to its storage in the format (nearest even; W
+    saturates; planes 0 and 1 stored as mu - 1/2), returned as the values it
+    represents."""
+    g = np.asarray(g, np.float64).copy()
+    _, vmax, _ = FMT[fmt]
+    g[6] = np.minimum(g[6], vmax)
+    g[:2] -= 0.5
+    g = _round_format(g, fmt)
+    g[:2] += 0.5
+    return g
+
+
+def host_gamma(t):
+    """A device state as the values it represents (float64): FP16/BF16 states
+    hold mu - 1/2 in planes 0 and 1."""
+    g = host(t).astype(np.float64)
+    if t.dtype in (torch.float16, torch.bfloat16):
+        g[:2] += 0.5
+    return g
+
+
 def ulp(v, fmt):
     """One unit in the last place of the format at |v| (subnormal floor)."""
     _, _, mant = FMT[fmt]
     v = np.maximum(np.abs(np.asarray(v, np.float64)), 2.0 ** -14 if fmt == "f16" else 2.0 ** -126)
     return 2.0 ** (np.floor(np.log2(v)) - mant)
+
+
+def ulp_gamma(g, fmt):
+    """One unit in the last place of each stored channel of state values g
+    (planes 0 and 1 are stored as mu - 1/2)."""
+    g = np.asarray(g, np.float64).copy()
+    g[:2] -= 0.5
+    return ulp(g, fmt)

@@ -15,7 +15,7 @@ import torch
 import oracle as O
 import paper_2112_09728_amd as pg
 from paper_2112_09728_amd import workload as wl
-from pgtest import (TOL_DIR, compare_samples, host, records_host, rel_err, round_storage, ulp,
+from pgtest import (TOL_DIR, compare_samples, host_gamma, records_host, rel_err, round_storage, ulp_gamma,
                     underflow_mask)
 
 pytestmark = [pytest.mark.gpu,
@@ -75,7 +75,7 @@ def test_batched_16_views_full_size():
     g1_dev = torch.empty_like(g_prev)
     pg.reproject(plain[crop_view].params(T - 1), cur.view, prev.view, g_prev, g1_dev)
     torch.cuda.synchronize()
-    g1_gpu = host(g1_dev).astype(np.float64)
+    g1_gpu = host_gamma(g1_dev)
     x0, y0 = 1792, 952
     rect = (x0, y0, x0 + 256, y0 + 256)
     c = (slice(None), slice(y0, y0 + 256), slice(x0, x0 + 256))
@@ -86,14 +86,14 @@ def test_batched_16_views_full_size():
 
     def within_one_ulp(got, want, ok, what):
         d = np.abs(got - want)
-        bound = ulp(want, "f16") + 1e-5 * (np.abs(want) + 1e-3)
+        bound = ulp_gamma(want, "f16") + 1e-5 * (np.abs(want) + 1e-3)
         over = (d > bound) & ok[None]
         say(f"  crop {what}: channels beyond 1 FP16 ulp: {int(over.sum())} of {over.size}; "
-            f"max d/ulp {float((d / ulp(want, 'f16'))[:, ok].max()):.2f}")
+            f"max d/ulp {float((d / ulp_gamma(want, 'f16'))[:, ok].max()):.2f}")
         assert over.sum() <= 1e-3 * over.size, what
         assert (got[7] == want[7]).all(), f"{what}: epochs differ"
 
-    g1_o, _ = O.reproject(P, v, vp, host(g_prev), rect=rect)
+    g1_o, _ = O.reproject(P, v, vp, host_gamma(g_prev), rect=rect)
     within_one_ulp(g1_gpu[c], round_storage(g1_o, "f16")[c], np.ones((256, 256), bool), "reprojection")
     rec_all = records_host(bg.samples[crop_view])
     ro = O.sample(P, v, g1_gpu, spp, rect=rect)
@@ -106,5 +106,5 @@ def test_batched_16_views_full_size():
     live = (rec_c["strategy"] == 1) | (rec_c["strategy"] == 2)
     assert rel_err(rec_c["radiance"][live], L[:, y0:y0 + 256, x0:x0 + 256][live]).max() <= 1e-5
     g2, stats = O.em(P, v, rec_all, g1_gpu, rect=rect, with_stats=True)
-    got = host(bg.state(crop_view)).astype(np.float64)
+    got = host_gamma(bg.state(crop_view))
     within_one_ulp(got[c], round_storage(g2, "f16")[c], ~underflow_mask(stats[:, y0:y0 + 256, x0:x0 + 256]), "EM")

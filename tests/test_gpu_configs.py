@@ -28,7 +28,7 @@ import paper_2112_09728_amd as pg
 from paper_2112_09728_amd import workload as wl
 from pgtest import (TOL_DIR, TOL_EM_FRAME, TOL_EM_RUN, assert_gamma_close, compare_samples, dev, gamma_errors,
                     host, records_host, rel_err, underflow_mask)
-from test_gpu_lowprec import round_storage, ulp
+from pgtest import host_gamma, round_storage, ulp_gamma
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
@@ -76,15 +76,25 @@ class OracleCone:
 
 
 def teacher_forced_crop(seed, t, fr, v_prev, gamma_prev, rec_gpu, gamma_gpu, crop, W, H, spp=1,
-                        storage=None):
+                        storage=None, reproj_gpu=None):
     """Step the crop from the GPU's previous state and records; returns
-    (sample stats, EM errors or ulp stats)."""
+    (sample stats, EM errors or ulp stats).  With a stored format, the
+    reprojection is checked within one unit of the format against the
+    storage-rounding oracle, and the sampling and EM steps are taken from the
+    GPU's own reprojected state reproj_gpu (the two roundings of a value that
+    lies near a boundary of the format may land one unit apart)."""
     P = O.params(seed, frame=t)
     v = O.OView(fr, fr["motion"], fr["disocc"])
     rr = grow(crop, 3, W, H)
     g1, _ = O.reproject(P, v, v_prev if v_prev is not None else v, gamma_prev if t else None, rect=rr)
     if storage:
         g1 = round_storage(g1, storage)
+        x0, y0, x1, y1 = rr
+        d = np.abs(reproj_gpu - g1)[:, y0:y1, x0:x1]
+        over = d > ulp_gamma(g1, storage)[:, y0:y1, x0:x1] + 1e-5 * (np.abs(g1[:, y0:y1, x0:x1]) + 1e-3)
+        assert over.sum() <= 1e-3 * over.size, f"reprojection: {int(over.sum())} channels beyond 1 ulp"
+        assert (reproj_gpu[7][y0:y1, x0:x1] == g1[7][y0:y1, x0:x1]).all()
+        g1 = reproj_gpu
     ro = O.sample(P, v, g1, spp, rect=rr)
     st, _ = compare_samples(rec_gpu, ro, pix_mask=crop_mask(rr, W, H), scene=fr, gamma=g1)
     assert st["dir_max"] <= TOL_DIR, st
@@ -94,11 +104,11 @@ def teacher_forced_crop(seed, t, fr, v_prev, gamma_prev, rec_gpu, gamma_gpu, cro
         return st, assert_gamma_close(gamma_gpu, g2, TOL_EM_FRAME, mask=ok, what=f"frame {t}")
     g2r = round_storage(g2, storage)
     d = np.abs(gamma_gpu - g2r)
-    bound = ulp(g2r, storage) + 1e-5 * (np.abs(g2r) + 1e-3)
+    bound = ulp_gamma(g2r, storage) + 1e-5 * (np.abs(g2r) + 1e-3)
     over = (d > bound) & ok[None]
     assert over.sum() <= 1e-3 * ok.sum() * 8, int(over.sum())
     assert (gamma_gpu[7][ok] == g2r[7][ok]).all()
-    return st, {"beyond_1ulp": int(over.sum()), "max_d_over_ulp": float((d / ulp(g2r, storage))[:, ok].max())}
+    return st, {"beyond_1ulp": int(over.sum()), "max_d_over_ulp": float((d / ulp_gamma(g2r, storage))[:, ok].max())}
 
 
 def free_run_table(name, g_gpu, g_orc, crop):
@@ -144,11 +154,16 @@ def test_1080p_pan_64_frames_crop():
         assert e[name].max() <= TOL_EM_RUN, name
 
 
-def test_4k_pan_64_frames_lowprec_crop():
+@pytest.mark.parametrize("W,H,crop", [(1920, 1080, (832, 412, 1088, 668)), (3840, 2160, (1792, 952, 2048, 1208))],
+                         ids=["1080p", "4k"])
+def test_pan_64_frames_lowprec_crop(W, H, crop):
+    """FP16/BF16 (and FP32) Gamma over the 64-frame pan: the last frame
+    against the storage-rounding oracle (implementation), and the
+    free-running stored states and their densities against the free-running
+    FP64 oracle on the crop (format error), printed per parameter."""
     cfg = wl.CONFIGS["1080p_4k_spp1_64f_fp16_bf16"]
-    W, H, seed, T = 3840, 2160, cfg["seed"], cfg["frames"]
-    crop = (1792, 952, 2048, 1208)
-    say(f"case: 4K pan {T} frames, FP16/BF16/FP32 Gamma, crop {crop}")
+    seed, T = cfg["seed"], cfg["frames"]
+    say(f"case: {W}x{H} pan {T} frames, FP16/BF16/FP32 Gamma, crop {crop}")
     seq = wl.Sequence(W, H, seed)
     cone = OracleCone(seed, 1, crop, T, W, H)
     dts = {"f16": torch.float16, "bf16": torch.bfloat16, "f32": torch.float32}
@@ -164,12 +179,16 @@ def test_4k_pan_64_frames_lowprec_crop():
         last = t == T - 1
         for k, g in guides.items():
             if last and k != "f32":
-                keep[k] = host(g.state).astype(np.float64)
+                keep[k] = host_gamma(g.state)
+                # the reprojected state this frame samples and trains with
+                tmp = torch.empty_like(g.state)
+                pg.reproject(g.params(t), cur.view, prev_dev.view, g.state, tmp)
+                keep[k + "_reproj"] = host_gamma(tmp)
             g.step(cur, prev_dev, frame=t)
             if last and k != "f32":
                 torch.cuda.synchronize()
                 keep[k + "_rec"] = records_host(g.samples)
-                keep[k + "_out"] = host(g.state).astype(np.float64)
+                keep[k + "_out"] = host_gamma(g.state)
         if last:
             v_last_prev = v_prev
             fr_last = fr
@@ -179,11 +198,11 @@ def test_4k_pan_64_frames_lowprec_crop():
     # implementation: the last frame against the storage-rounding oracle
     for k in ("f16", "bf16"):
         st, u = teacher_forced_crop(seed, T - 1, fr_last, v_last_prev, keep[k], keep[k + "_rec"], keep[k + "_out"],
-                                    crop, W, H, storage=k)
+                                    crop, W, H, storage=k, reproj_gpu=keep[k + "_reproj"])
         say(f"  {k} frame {T - 1} vs storage-rounding oracle: samples dir max {st['dir_max']:.2e}, "
             f"flips {st['flips']}; {u}")
     # format error: free-running states against the FP64 oracle
-    errs = {k: free_run_table(k, host(g.state), cone.gamma, crop) for k, g in guides.items()}
+    errs = {k: free_run_table(k, host_gamma(g.state), cone.gamma, crop) for k, g in guides.items()}
     # densities of one set of directions under each stored state and under the FP64 state
     v = O.OView(fr_last, fr_last["motion"], fr_last["disocc"])
     P = O.params(seed, frame=T - 1)
