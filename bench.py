@@ -200,10 +200,16 @@ def main():
     # again from a new state: the warm-up frames from frame 0, whose first
     # frame (every model new, k = 0, N(0) = 20 picks) is timed on its own,
     # then the timed frames
+    clean = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
     for t in range(frames):
         frame(t)
     torch.cuda.synchronize()
     reset_state(guide)
+    # read 1 GiB of clean lines so that frame 0 does not write back the
+    # dirty lines the reset left in the Infinity Cache
+    clean.sum()
+    torch.cuda.synchronize()
+    del clean
     ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     for t in range(a.warmup):
         frame(t, ev0 if t == 0 else None)
@@ -414,7 +420,23 @@ def bench_batched(a):
     ms_graph = timed(lambda t: bgg.step(pairs(t), t, graph=True))
     same = same and all(torch.equal(bgg.state(i).view(torch.int16), plain[i].state.view(torch.int16))
                         for i in range(len(vs)))
-    print(f"bench: batched16 plain {ms_plain:.3f} ms, batched eager {ms_eager:.3f} ms, graph {ms_graph:.3f} ms; "
+    # the plain launch sequences again with the tiles the autotuner picked,
+    # which separates the gain of batching from that of the tile choice
+    plain_t = []
+    for s in specs:
+        tw, th = bg.tile_of(s["spp"])
+        plain_t.append(pg.Guide(s["width"], s["height"], s["lights"], s["ambient"], spp=s["spp"], seed=s["seed"],
+                                view_id=s["view"], gamma_dtype=torch.float16, tile_w=tw, tile_h=th))
+
+    def run_plain_tuned(t):
+        for i, g in enumerate(plain_t):
+            g.step(dev[t][i], dev[t - 1][i] if t else None, frame=t)
+
+    ms_plain_tuned = timed(run_plain_tuned)
+    same = same and all(torch.equal(plain_t[i].state.view(torch.int16), plain[i].state.view(torch.int16))
+                        for i in range(len(vs)))
+    print(f"bench: batched16 plain {ms_plain:.3f} ms, plain with the tuned tiles {ms_plain_tuned:.3f} ms, "
+          f"batched eager {ms_eager:.3f} ms, graph {ms_graph:.3f} ms; "
           f"tile {bg.tile}; autotuner {tune}", file=sys.stderr, flush=True)
     G = 16
     bytes_px = sum(w * h * (bytes_reproject_sample(G, spp) + 1 + 4 * spp + bytes_em(G, spp))
@@ -440,8 +462,10 @@ def bench_batched(a):
             "tile_per_spp": {str(k): list(v) for k, v in sorted(bg.tile.items())},
         },
         "plain_ms_per_step": round(ms_plain, 4),
+        "plain_tuned_tiles_ms_per_step": round(ms_plain_tuned, 4),
         "batched_eager_ms_per_step": round(ms_eager, 4),
         "speedup_vs_plain": round(ms_plain / ms_graph, 3),
+        "speedup_vs_plain_tuned_tiles": round(ms_plain_tuned / ms_graph, 3),
         "identical_to_plain": bool(same),
         "roofline": {"bound": "hbm", "kernel": "k_rs_batched + k_em_batched", "achieved": round(gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),

@@ -27,6 +27,13 @@ __device__ __forceinline__ float dot3(V3 a, V3 b) { return fmaf(a.z, b.z, fmaf(a
 // the per-sample paths use these instead wherever the argument is known to
 // be a normal number.
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+// Element i of an array whose base is uniform across the wave, with i taken
+// as an unsigned 32-bit offset: the access then uses the scalar-base plus
+// vector-offset form instead of 64-bit address arithmetic in every lane.
+template <typename T>
+__device__ __forceinline__ T &at(T *p, int i) {
+  return p[(uint32_t)i];
+}
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ---------------------------------------------------------------------------
@@ -140,20 +147,21 @@ __device__ __forceinline__ V3 sq2hemi(float ux, float uy) {
   return V3{k * c, k * s, 1.0f - r2};
 }
 
-// atan on [-1, 1]: odd polynomial t * P(t^2) of degree 17, coefficients
-// fitted for this library (max error 5.8e-9 in exact arithmetic, about
-// 1.4 ulp evaluated in FP32 by Horner's rule).
-__device__ __forceinline__ float atan_unit(float t) {
+// (4/pi) atan(t) on [-1, 1]: odd polynomial t * P(t^2) of degree 17, the
+// coefficients of a fit of atan made for this library (max error 5.8e-9 in
+// exact arithmetic) multiplied by 4/pi and rounded to FP32 (max error
+// 4.3e-8 of the scaled function, below half an ulp of its values near 1).
+__device__ __forceinline__ float atan_4pi_unit(float t) {
   const float s = t * t;
-  float p = 2.456724411e-03f;
-  p = fmaf(p, s, -1.440135855e-02f);
-  p = fmaf(p, s, 3.978122771e-02f);
-  p = fmaf(p, s, -7.234857976e-02f);
-  p = fmaf(p, s, 1.049894691e-01f);
-  p = fmaf(p, s, -1.416122913e-01f);
-  p = fmaf(p, s, 1.998590678e-01f);
-  p = fmaf(p, s, -3.333259821e-01f);
-  p = fmaf(p, s, 9.999998808e-01f);
+  float p = 3.127998672e-03f;
+  p = fmaf(p, s, -1.833637990e-02f);
+  p = fmaf(p, s, 5.065103248e-02f);
+  p = fmaf(p, s, -9.211707115e-02f);
+  p = fmaf(p, s, 1.336767375e-01f);
+  p = fmaf(p, s, -1.803063750e-01f);
+  p = fmaf(p, s, 2.544684708e-01f);
+  p = fmaf(p, s, -4.244038165e-01f);
+  p = fmaf(p, s, 1.273239374e+00f);
   return t * p;
 }
 
@@ -170,11 +178,10 @@ __device__ __forceinline__ void hemi2sq(V3 w, float &ux, float &uy) {
   const float den = bigx ? w.x : w.y;
   const float t = den != 0.0f ? num * __builtin_amdgcn_rcpf(den) : 0.0f;
   const float r = copysignf(rho, den);
-  const float o = r * k4OverPi * atan_unit(t);
+  const float o = r * atan_4pi_unit(t);
   ux = fmaf(0.5f, bigx ? r : o, 0.5f);
   uy = fmaf(0.5f, bigx ? o : r, 0.5f);
 }
-
 // ---------------------------------------------------------------------------
 // Synthetic material: Lambert + GGX (Walter et al., EGSR 2007) with Smith G1
 // and Schlick F, alpha = roughness^2.  Sampling density
@@ -187,7 +194,8 @@ struct Pixel {
   float a2_pi;      // alpha^2 / pi
   float g1_wo_over_2wo;  // G1(wo) / (2 wo_z)
   float f0, s_d, s_d_pi;
-  float one_m_f0, one_m_sd;  // 1 - f0, 1 - s_d
+  float one_m_f0;   // 1 - f0
+  float one_m_sd_q;  // (1 - s_d) / 4
 };
 
 __device__ __forceinline__ float smith_g1(V3 v, float alpha2) {
@@ -201,7 +209,8 @@ __device__ __forceinline__ float smith_g1(V3 v, float alpha2) {
 //   p_ggx = D h_z/(4 wo.h) = alpha^2 |h|^4 h_z / (4 pi den^2 (wo.h))
 //   G1(wi) / wi_z          = 2 / (wi_z + q)
 //   f_spec = F D G1(wi) G1(wo) / (4 wi_z wo_z) = F D (G1(wo)/(2 wo_z)) / (wi_z + q)
-// and R = 1 / (den^2 (wo.h) (wi_z + q)) serves both denominators.
+// and R = 1 / (den^2 (wo.h) (wi_z + q)) serves both denominators (the 1/4
+// of p_ggx rides on the constant (1 - s_d) / 4).
 __device__ __forceinline__ void brdf_eval(const Pixel &px, V3 wi, float &f, float &pdf) {
   const V3 h = V3{px.wo.x + wi.x, px.wo.y + wi.y, px.wo.z + wi.z};
   const float hh = dot3(h, h);
@@ -211,8 +220,8 @@ __device__ __forceinline__ void brdf_eval(const Pixel &px, V3 wi, float &f, floa
   const float woh_u = dot3(px.wo, h);  // |h| (wo . h_hat)
   const float R = __builtin_amdgcn_rcpf(den * den * woh_u * wq);
   const float A = px.a2_pi * hh * hh;  // D den^2
-  const float pggx = 0.25f * A * h.z * wq * R;
-  pdf = fmaf(px.s_d_pi, wi.z, px.one_m_sd * pggx);
+  const float pggx4 = A * h.z * wq * R;  // 4 p_ggx
+  pdf = fmaf(px.s_d_pi, wi.z, px.one_m_sd_q * pggx4);
   const float woh = woh_u * __builtin_amdgcn_rsqf(hh);
   const float m = 1.0f - woh;
   const float m2 = m * m;
@@ -225,8 +234,8 @@ __device__ __forceinline__ float brdf_pdf_only(const Pixel &px, V3 wi) {
   const float hh = dot3(h, h);
   const float den = fmaf(px.alpha2, h.z * h.z, fmaf(h.x, h.x, h.y * h.y));
   const float R = frcp(den * den * dot3(px.wo, h));
-  const float pggx = 0.25f * px.a2_pi * hh * hh * h.z * R;
-  return fmaf(px.s_d_pi, wi.z, px.one_m_sd * pggx);
+  const float pggx4 = px.a2_pi * hh * hh * h.z * R;  // 4 p_ggx
+  return fmaf(px.s_d_pi, wi.z, px.one_m_sd_q * pggx4);
 }
 
 // ---------------------------------------------------------------------------
@@ -259,6 +268,32 @@ __device__ __forceinline__ float gauss_q(const Gauss &g, float ux, float uy) {
   return fmaf(z1, z1, z2 * z2);
 }
 
+// The weighted Gaussian term pi N(u) / (2 pi) of a lobe as the E-step
+// evaluates it, at a point given relative to the lobe's mean (r = u - mu,
+// exact near the mean):
+//   pi_norm exp2(-log2(e)/2 (z1^2 + z2^2)),  z1 = i11 rx,  z2 = i22 ry + c21 z1,
+// the whitening L^-1 (u - mu) with c21 = -l21 i22, and pi_norm =
+// pi / (4 pi^2 l11 l22).  (Folding sqrt(log2(e)/2) into i11 and i22 saves one
+// multiplication but rounds the scale twice and squares it, which the far
+// tail of a lobe carries into the weights: kept separate.)
+struct LobeTerm {
+  float mx, my, i11, i22, c21, pi_norm;
+};
+__device__ __forceinline__ LobeTerm lobe_term(const Gauss &g, float pi) {
+  LobeTerm t;
+  t.mx = g.mx;
+  t.my = g.my;
+  t.i11 = g.i11;
+  t.i22 = g.i22;
+  t.c21 = -g.l21 * g.i22;
+  t.pi_norm = pi * g.norm;
+  return t;
+}
+__device__ __forceinline__ float lobe_eval(const LobeTerm &t, float rx, float ry) {
+  const float z1 = rx * t.i11;
+  const float z2 = fmaf(ry, t.i22, z1 * t.c21);
+  return t.pi_norm * __builtin_amdgcn_exp2f(-0.72134752044448170368f * fmaf(z1, z1, z2 * z2));
+}
 // Solid-angle density N(u)/(2 pi), accurate exponential.
 __device__ __forceinline__ float gauss_pdf_acc(const Gauss &g, float ux, float uy) {
   return g.norm * expf(-0.5f * gauss_q(g, ux, uy));
@@ -311,24 +346,27 @@ template <> struct MuOffset<float> { static constexpr float v = 0.0f; };
 // Channel c of a state as stored (the offset taken off mu, W saturated).
 template <typename T>
 __device__ __forceinline__ void gamma_put(T *p, int c, float v) {
-  if (c < 2) v -= MuOffset<T>::v;
+  if constexpr (MuOffset<T>::v != 0.0f)
+    if (c < 2) v -= MuOffset<T>::v;
   if (c == 6) v = fminf(v, GammaIO<T>::kMax);
   GammaIO<T>::store(p, v);
 }
 template <typename T>
 __device__ __forceinline__ float gamma_get(const T *p, int c) {
-  return GammaIO<T>::load(p) + (c < 2 ? MuOffset<T>::v : 0.0f);
+  // (x + 0 is no identity for x = -0, so FP32 states skip the add)
+  if constexpr (MuOffset<T>::v != 0.0f) return GammaIO<T>::load(p) + (c < 2 ? MuOffset<T>::v : 0.0f);
+  return GammaIO<T>::load(p);
 }
 
 template <typename T>
 __device__ __forceinline__ void gamma_load(const T *g, int plane, int idx, float out[8]) {
 #pragma unroll
-  for (int c = 0; c < 8; ++c) out[c] = gamma_get(g + c * plane + idx, c);
+  for (int c = 0; c < 8; ++c) out[c] = gamma_get(&at(g + c * plane, idx), c);
 }
 template <typename T>
 __device__ __forceinline__ void gamma_store(T *g, int plane, int idx, const float in[8]) {
 #pragma unroll
-  for (int c = 0; c < 8; ++c) gamma_put(g + c * plane + idx, c, in[c]);
+  for (int c = 0; c < 8; ++c) gamma_put(&at(g + c * plane, idx), c, in[c]);
 }
 
 }  // namespace pgk

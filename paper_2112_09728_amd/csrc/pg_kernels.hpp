@@ -24,6 +24,9 @@ struct ParamsK {
   float pi_init, pi_lo, pi_hi, eps, tau_z, tau_n, rough_min, s_d, f0;
   uint32_t flags;
   float stale_tau;
+  // material constants derived on the host (FP32, as the device would round
+  // them), so that kernels take them as uniform operands
+  float s_d_pi, one_m_f0, one_m_sd_q;  // s_d / pi, 1 - f0, (1 - s_d) / 4
 };
 
 struct SamplesK {
@@ -59,7 +62,7 @@ __device__ __forceinline__ void stream_xy(int W, int H, int &x, int &y) {
 }
 
 __device__ __forceinline__ V3 load3(const float *p, int plane, int idx) {
-  return V3{p[idx], p[plane + idx], p[2 * plane + idx]};
+  return V3{at(p, idx), at(p + plane, idx), at(p + 2 * plane, idx)};
 }
 
 __device__ __forceinline__ void gamma_reset(const ParamsK &P, float g[8]) {
@@ -85,9 +88,9 @@ __device__ __forceinline__ Pixel make_pixel(const ParamsK &P, V3 n, V3 o, float 
   px.g1_wo_over_2wo = smith_g1(px.wo, px.alpha2) * frcp(2.0f * px.wo.z);
   px.f0 = P.f0;
   px.s_d = P.s_d;
-  px.s_d_pi = P.s_d * kInvPi;
-  px.one_m_f0 = 1.0f - P.f0;
-  px.one_m_sd = 1.0f - P.s_d;
+  px.s_d_pi = P.s_d_pi;
+  px.one_m_f0 = P.one_m_f0;
+  px.one_m_sd_q = P.one_m_sd_q;
   return px;
 }
 
@@ -478,12 +481,12 @@ __device__ __forceinline__ void stage_records(const ViewK &v, const SamplesK &S,
       px[i] = py[i] = pz[i] = pl[i] = pp[i] = 0.0f;
       if (in[i]) {
         const int o = s * plane + gi[i];
-        st[i] = S.strat[o];
-        pp[i] = S.pb[o];
-        px[i] = S.dir[o];
-        py[i] = S.dir[splane + o];
-        pz[i] = S.dir[2 * splane + o];
-        pl[i] = S.L[o];
+        st[i] = at(S.strat, o);
+        pp[i] = at(S.pb, o);
+        px[i] = at(S.dir, o);
+        py[i] = at(S.dir + splane, o);
+        pz[i] = at(S.dir + 2 * splane, o);
+        pl[i] = at(S.L, o);
       }
     }
 #pragma unroll
@@ -501,33 +504,44 @@ __device__ __forceinline__ void stage_records(const ViewK &v, const SamplesK &S,
 }
 
 // Running sums of one E-step: B0 = sum w, B1 = sum w gamma, and the
-// weighted mean (mx, my) and normalised scatter (sxx, sxy, syy) of u under the
-// weights v = w gamma, updated per sample in the pairwise form
-//   m += (v / B1') d,   S = (B1 / B1') (S + (v / B1') d d^T),   d = u - m,
-// which has no cancellation when a heavy sample follows light ones.  A
-// Gaussian weight below FP32's normal range counts as no evidence, so the
-// reciprocal of B1' is always of a normal number.
+// weighted mean (mx, my) and normalised scatter (sxx, sxy, syy) of the
+// samples' points under the weights v = w gamma, updated per sample in the
+// pairwise form
+//   m += (v / B1') d,   S = (B1 / B1') (S + (v / B1') d d^T),   d = r - m,
+// which has no cancellation when a heavy sample follows light ones.  The
+// points are r = u - mu, relative to the lobe's mean before the step (the
+// value the Gaussian term needs anyway, exact near the mean); accum_to_unit
+// adds the mean back once, after the last sample.  A Gaussian weight below
+// FP32's normal range counts as no evidence, so the reciprocal of B1' is
+// always of a normal number.
 struct Accum {
   float B0, B1, mx, my, sxx, sxy, syy;
 };
 
+// The mean of the points r = u - mu back to u (the scatter is the same).
+__device__ __forceinline__ void accum_to_unit(Accum &a, const LobeTerm &t) {
+  a.mx += t.mx;
+  a.my += t.my;
+}
+
 struct EmCtx {
   Pixel px;
-  Gauss G;
-  float pi, one_m_pi;
-  float pi_norm;  // pi / (4 pi^2 l11 l22): the Gaussian term of D up to its exponential
+  LobeTerm T;  // the lobe's Gaussian term in the centred square
+  float one_m_pi;
 };
 
 // One training sample of a list (its staged record is never zero: lists
-// hold only BRDF-strategy records inside the image).
+// hold only BRDF-strategy records inside the image).  Mean and scatter
+// accumulate relative to the lobe's centre (see Accum).
 __device__ __forceinline__ void em_visit(const EmCtx &c, float4 r, Accum &a) {
   const V3 l = to_local(c.px.f, V3{r.x, r.y, r.z});
   if (l.z <= 0.0f) return;
   float ux, uy, f, pb;
   hemi2sq(l, ux, uy);
+  const float rx = ux - c.T.mx, ry = uy - c.T.my;
   brdf_eval(c.px, l, f, pb);
   const float w = r.w * f * l.z;
-  const float ga = c.pi_norm * __builtin_amdgcn_exp2f(-0.72134752044448170368f * gauss_q(c.G, ux, uy));
+  const float ga = lobe_eval(c.T, rx, ry);
   const float gb = c.one_m_pi * pb;
   const float gam = ga * __builtin_amdgcn_rcpf(fmaxf(ga + gb, 1.17549435e-38f));
   a.B0 += w;
@@ -537,7 +551,7 @@ __device__ __forceinline__ void em_visit(const EmCtx &c, float4 r, Accum &a) {
     const float rb = __builtin_amdgcn_rcpf(bn);
     const float fr = vw * rb, keep = a.B1 * rb;
     a.B1 = bn;
-    const float dx = ux - a.mx, dy = uy - a.my;
+    const float dx = rx - a.mx, dy = ry - a.my;
     a.mx = fmaf(dx, fr, a.mx);
     a.my = fmaf(dy, fr, a.my);
     const float fx = fr * dx, fy = fr * dy;
@@ -603,7 +617,14 @@ __device__ __forceinline__ int n_picks(const ParamsK &P, int k) {
   return 5 + (15 * (P.k_max - k)) / P.k_max;
 }
 
-// Training list of one pixel: the LDS indices of its kept candidates, in the
+// A list entry is the byte offset of its staged record from the start of the
+// records area (below 64 KiB: the area is part of one block's LDS), so that
+// the record's LDS address is the entry plus a constant.
+__device__ __forceinline__ float4 list_record(const float4 *lds, uint32_t off) {
+  return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(lds) + off);
+}
+
+// Training list of one pixel: the LDS byte offsets of its kept candidates, in the
 // order of the training set (own samples by sample index, then picks by pick
 // index), stored in column `col` of the list area.  A candidate is kept when
 // its staged record is a BRDF-strategy sample inside the image.  Candidates
@@ -625,7 +646,7 @@ __device__ __forceinline__ int build_list(const ParamsK &P, const float4 *lds, c
 #pragma unroll
     for (int s = 0; s < kMaxSpp; ++s)
       if (s < spp) {
-        list[n * NT + col] = (uint16_t)(s * SA + own);
+        list[n * NT + col] = (uint16_t)((s * SA + own) << 4);
         n += wv[s] != 0.0f ? 1 : 0;
       }
   }
@@ -645,7 +666,7 @@ __device__ __forceinline__ int build_list(const ParamsK &P, const float4 *lds, c
 #pragma unroll
     for (int j = 0; j < 8; ++j)
       if (m0 + j < npick) {
-        list[n * NT + col] = (uint16_t)e[j];
+        list[n * NT + col] = (uint16_t)(e[j] << 4);
         n += wv[j] != 0.0f ? 1 : 0;
       }
   }
@@ -665,7 +686,7 @@ __device__ __forceinline__ bool stale_history(const ParamsK &P, const Pixel &px,
   const float pi = g[5], pi0 = P.pi_init;
   float lm = 0.0f, lr = 0.0f, ws = 0.0f;
   for (int j = 0; j < len; ++j) {
-    const float4 r = lds[list[j * nt + me]];
+    const float4 r = list_record(lds, list[j * nt + me]);
     const V3 l = to_local(px.f, V3{r.x, r.y, r.z});
     if (l.z <= 0.0f) continue;
     float ux, uy, f, pb;
@@ -753,8 +774,8 @@ __device__ __forceinline__ void em_load(const ViewK &v, const SamplesK &S, const
   if (x0 < v.W && y0 < v.H) {
     const int idx0 = y0 * v.pitch + x0;
     gamma_load(gamma, plane, idx0, R.g);
-    R.alb = v.alb[idx0];
-    R.rough = v.rough[idx0];
+    R.alb = at(v.alb, idx0);
+    R.rough = at(v.rough, idx0);
     R.n = load3(v.n, plane, idx0);
     R.o = load3(v.o, plane, idx0);
   }
@@ -770,12 +791,12 @@ __device__ __forceinline__ void em_load(const ViewK &v, const SamplesK &S, const
     R.px[i] = R.py[i] = R.pz[i] = R.pl[i] = R.pp[i] = 0.0f;
     if (e < In::SA && gx >= 0 && gy >= 0 && gx < v.W && gy < v.H) {
       const int o = gy * v.pitch + gx;
-      R.st[i] = S.strat[o];
-      R.pp[i] = S.pb[o];
-      R.px[i] = S.dir[o];
-      R.py[i] = S.dir[splane + o];
-      R.pz[i] = S.dir[2 * splane + o];
-      R.pl[i] = S.L[o];
+      R.st[i] = at(S.strat, o);
+      R.pp[i] = at(S.pb, o);
+      R.px[i] = at(S.dir, o);
+      R.py[i] = at(S.dir + splane, o);
+      R.pz[i] = at(S.dir + 2 * splane, o);
+      R.pl[i] = at(S.L, o);
     }
   }
 }
@@ -844,19 +865,18 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
   if (len > 0) {
     const int idx = (ty0 + me / TW) * v.pitch + tx0 + me % TW;
     gamma_load(gamma, plane, idx, g);
-    c.px = make_pixel(P, load3(v.n, plane, idx), load3(v.o, plane, idx), v.rough[idx], v.alb[idx]);
+    c.px = make_pixel(P, load3(v.n, plane, idx), load3(v.o, plane, idx), at(v.rough, idx), at(v.alb, idx));
     if (STALE && !batch && g[7] >= 1.0f && stale_history(P, c.px, g, lds, list, me, len, NT)) gamma_reset(P, g);
   }
   if (len > 0) {  // otherwise no training sample (or no pixel): the model stays as it is
     const int iters = batch ? iterations : 1;
     for (int it = 0; it < iters; ++it) {
-      c.G = gauss_setup(g[0], g[1], g[2], g[3], g[4], P.eps);
-      c.pi = g[5];
+      c.T = lobe_term(gauss_setup(g[0], g[1], g[2], g[3], g[4], P.eps), g[5]);
       c.one_m_pi = 1.0f - g[5];
-      c.pi_norm = g[5] * c.G.norm;
       Accum a = {0, 0, 0, 0, 0, 0, 0};
-      for (int j = 0; j < len; ++j) em_visit(c, lds[list[j * NT + me]], a);
+      for (int j = 0; j < len; ++j) em_visit(c, list_record(lds, list[j * NT + me]), a);
       if (!(a.B0 > 0.0f)) break;
+      accum_to_unit(a, c.T);
       if (!batch) {
         // stepwise merge with eta = 1/(k+1) and evidence W; only ratios of
         // evidences appear, so a subnormal B1 is harmless

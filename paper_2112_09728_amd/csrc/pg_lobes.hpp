@@ -272,8 +272,8 @@ __global__ __launch_bounds__(256) void k_lobes_pdf(ParamsK P, ViewK v, const flo
 template <int K>
 struct LobesCtx {
   Pixel px;
-  Gauss G[K];
-  float pi[K], one_m_tot;
+  LobeTerm T[K];  // each lobe's Gaussian term in the centred square
+  float one_m_tot;
   V3 xp;  // positional reuse: the pixel's position relative to the tile's reference point
 };
 
@@ -300,10 +300,12 @@ __device__ __forceinline__ void lobes_visit(const LobesCtx<K> &c, float4 r, floa
   hemi2sq(l, ux, uy);
   brdf_eval(c.px, l, f, pb);
   const float w = r.w * f * l.z;
-  float ga[K], D = c.one_m_tot * pb;
+  float ga[K], rx[K], ry[K], D = c.one_m_tot * pb;
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    ga[j] = c.pi[j] * gauss_pdf_fast(c.G[j], ux, uy);
+    rx[j] = ux - c.T[j].mx;  // relative to lobe j's mean (see Accum)
+    ry[j] = uy - c.T[j].my;
+    ga[j] = lobe_eval(c.T[j], rx[j], ry[j]);
     D += ga[j];
   }
   const float rD = __builtin_amdgcn_rcpf(fmaxf(D, 1.17549435e-38f));
@@ -316,7 +318,7 @@ __device__ __forceinline__ void lobes_visit(const LobesCtx<K> &c, float4 r, floa
       const float rb = __builtin_amdgcn_rcpf(bn);
       const float fr = vw * rb, keep = a[j].B1 * rb;
       a[j].B1 = bn;
-      const float dx = ux - a[j].mx, dy = uy - a[j].my;
+      const float dx = rx[j] - a[j].mx, dy = ry[j] - a[j].my;
       a[j].mx = fmaf(dx, fr, a[j].mx);
       a[j].my = fmaf(dy, fr, a[j].my);
       const float fx = fr * dx, fy = fr * dy;
@@ -363,13 +365,13 @@ __device__ __forceinline__ void stage_records_vpl(const ViewK &v, const SamplesK
       px[i] = py[i] = pz[i] = pl[i] = pp[i] = th[i] = 0.0f;
       if (in[i]) {
         const int o = s * plane + gi[i];
-        st[i] = S.strat[o];
-        pp[i] = S.pb[o];
-        px[i] = S.dir[o];
-        py[i] = S.dir[splane + o];
-        pz[i] = S.dir[2 * splane + o];
-        pl[i] = S.L[o];
-        th[i] = hit[o];
+        st[i] = at(S.strat, o);
+        pp[i] = at(S.pb, o);
+        px[i] = at(S.dir, o);
+        py[i] = at(S.dir + splane, o);
+        pz[i] = at(S.dir + 2 * splane, o);
+        pl[i] = at(S.L, o);
+        th[i] = at(hit, o);
       }
     }
 #pragma unroll
@@ -393,7 +395,7 @@ __device__ __forceinline__ void stage_records_vpl(const ViewK &v, const SamplesK
   }
 }
 
-// E-step of one pixel over its training list (LDS indices list[j * stride])
+// E-step of one pixel over its training list (LDS byte offsets list[j * stride])
 // and the stepwise merge of every lobe, in place on g.  A list whose samples
 // carry no weight leaves g as it is.
 template <int K, bool VPL = false>
@@ -403,21 +405,23 @@ __device__ __forceinline__ void lobes_update(const ParamsK &P, const ViewK &v, i
   const int plane = v.H * v.pitch;
   LobesCtx<K> c;
   c.xp = xp;
-  c.px = make_pixel(P, load3(v.n, plane, idx), load3(v.o, plane, idx), v.rough[idx], v.alb[idx]);
+  c.px = make_pixel(P, load3(v.n, plane, idx), load3(v.o, plane, idx), at(v.rough, idx), at(v.alb, idx));
   float tot = 0.0f;
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    c.G[j] = gauss_setup(g[6 * j], g[6 * j + 1], g[6 * j + 2], g[6 * j + 3], g[6 * j + 4], P.eps);
-    c.pi[j] = g[6 * j + 5];
-    tot += c.pi[j];
+    c.T[j] = lobe_term(gauss_setup(g[6 * j], g[6 * j + 1], g[6 * j + 2], g[6 * j + 3], g[6 * j + 4], P.eps),
+                       g[6 * j + 5]);
+    tot += g[6 * j + 5];
   }
   c.one_m_tot = 1.0f - tot;
   float B0 = 0.0f;
   Accum a[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) a[j] = Accum{0, 0, 0, 0, 0, 0, 0};
-  for (int j = 0; j < len; ++j) lobes_visit<K, VPL>(c, lds[list[j * stride]], B0, a);
+  for (int j = 0; j < len; ++j) lobes_visit<K, VPL>(c, list_record(lds, list[j * stride]), B0, a);
   if (!(B0 > 0.0f)) return;
+#pragma unroll
+  for (int j = 0; j < K; ++j) accum_to_unit(a[j], c.T[j]);  // mean and scatter back to u
   const float Wv = g[6 * K], kk = g[6 * K + 1];
   const float eta = frcp(kk + 1.0f);
   const float sw = fmaf(1.0f - eta, Wv, eta * B0);

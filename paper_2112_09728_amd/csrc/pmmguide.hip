@@ -114,6 +114,9 @@ ParamsK to_k(const pg_params *p) {
   k.f0 = p->f0;
   k.flags = p->flags;
   k.stale_tau = p->stale_tau;
+  k.s_d_pi = p->s_diffuse * 0.318309886183790671538f;
+  k.one_m_f0 = 1.0f - p->f0;
+  k.one_m_sd_q = 0.25f * (1.0f - p->s_diffuse);
   return k;
 }
 

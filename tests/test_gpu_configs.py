@@ -8,7 +8,9 @@ frame arrays; teacher-forced checks step the crop (grown by the 3 px the picks
 need) from the GPU's previous state and records.
 
 * 1920x1080, spp 1, 64-frame pan, FP32 Gamma: the 256x256 crop at (832, 412)
-  teacher-forced at every frame, and free-running after 64 frames.
+  teacher-forced at every frame, and free-running after 64 frames (bounded
+  through a twin of the oracle's run whose state is rounded to FP32 every
+  frame, see assert_free_run).
 * 3840x2160, spp 1, 64-frame pan, Gamma stored as FP16 and BF16 (and FP32 for
   reference): per-parameter and per-density errors on the crop at
   (1792, 952) against the free-running FP64 oracle, and the last frame against
@@ -26,7 +28,7 @@ import torch
 import oracle as O
 import paper_2112_09728_amd as pg
 from paper_2112_09728_amd import workload as wl
-from pgtest import (TOL_DIR, TOL_EM_FRAME, TOL_EM_RUN, assert_gamma_close, compare_samples, dev, gamma_errors,
+from pgtest import (TOL_DIR, TOL_EM_FRAME, assert_gamma_close, compare_samples, dev, gamma_errors,
                     host, records_host, rel_err, underflow_mask)
 from pgtest import host_gamma, round_storage, ulp_gamma
 
@@ -53,10 +55,13 @@ def crop_mask(rect, W, H):
 
 
 class OracleCone:
-    """FP64 free run of the oracle on the dependency cone of a crop."""
+    """FP64 free run of the oracle on the dependency cone of a crop.  With
+    round32 the state is rounded to FP32 after every frame: the oracle's own
+    trajectory under a perturbation of FP32's size."""
 
-    def __init__(self, seed, spp, crop, frames, W, H):
+    def __init__(self, seed, spp, crop, frames, W, H, round32=False):
         self.seed, self.spp, self.crop, self.T, self.W, self.H = seed, spp, crop, frames, W, H
+        self.round32 = round32
         self.v_prev = None
         self.gamma = None
 
@@ -71,6 +76,8 @@ class OracleCone:
         rec["radiance"] = O.light(fr["lights"], float(fr["ambient"]), fr["vis"], rec["dir"],
                                   rec["strategy"], rect=rr)
         self.gamma = O.em(P, v, rec, g1, rect=R)
+        if self.round32:
+            self.gamma = self.gamma.astype(np.float32).astype(np.float64)
         self.v_prev = v
         return v
 
@@ -120,12 +127,36 @@ def free_run_table(name, g_gpu, g_orc, crop):
     return e
 
 
+# A free-running FP32 state drifts from the FP64 one by the per-frame
+# rounding, carried and at some pixels amplified by the trajectory (the EM
+# map of a lobe still moving amplifies changes of its inputs).  The twin
+# cone measures that carrying on the oracle itself: the same FP64 run with
+# its state rounded to FP32 after every frame.  Each quantile of the GPU's
+# error (median to max) is bounded by the one-step tolerance or by
+# TWIN_FACTOR times the twin's error at that quantile (the GPU's per-frame
+# arithmetic rounds a few times more than storing the state does), and by
+# FREE_RUN_CAP everywhere.
+TWIN_FACTOR = 10.0
+FREE_RUN_CAP = 1e-3
+
+
+def assert_free_run(e, e_twin, what):
+    assert (e["k"] == 0).all(), f"{what}: epochs differ"
+    for name in ("mu", "sigma", "pi", "W"):
+        g, tw = np.asarray(e[name], float).ravel(), np.asarray(e_twin[name], float).ravel()
+        assert g.max() <= FREE_RUN_CAP, (what, name, g.max())
+        for q in (0.5, 0.9, 0.99, 0.999, 1.0):
+            gq, tq = np.quantile(g, q), np.quantile(tw, q)
+            assert gq <= max(TOL_EM_FRAME, TWIN_FACTOR * tq), (what, name, q, gq, tq)
+
+
 def test_1080p_pan_64_frames_crop():
     cfg = wl.CONFIGS["1080p_spp1_64f_fp32_pan"]
     W, H, seed, crop, T = 1920, 1080, cfg["seed"], cfg["crop"], cfg["frames"]
     say(f"case: 1080p pan {T} frames, crop {crop}")
     seq = wl.Sequence(W, H, seed)
     cone = OracleCone(seed, 1, crop, T, W, H)
+    twin = OracleCone(seed, 1, crop, T, W, H, round32=True)
     guide = None
     prev_dev = v_prev = None
     worst = {}
@@ -144,14 +175,14 @@ def test_1080p_pan_64_frames_crop():
         worst["dir"] = max(worst.get("dir", 0.0), st["dir_max"])
         worst["flips"] = worst.get("flips", 0) + st["flips"]
         v_prev = cone.step(t, fr)
+        twin.step(t, fr)
         prev_dev = cur
     say(f"  teacher-forced, worst over {T} frames: {worst}")
     e = free_run_table("f32", host(guide.state), cone.gamma, crop)
+    e_twin = free_run_table("twin", twin.gamma, cone.gamma, crop)
     k = host(guide.state)[7, crop[1]:crop[3], crop[0]:crop[2]]
     say(f"  k after {T} frames: mean {k.mean():.2f}, share at kMax {(k == 16).mean():.3f}")
-    assert (e["k"] == 0).all()
-    for name in ("mu", "sigma", "pi", "W"):
-        assert e[name].max() <= TOL_EM_RUN, name
+    assert_free_run(e, e_twin, "1080p free run")
 
 
 @pytest.mark.parametrize("W,H,crop", [(1920, 1080, (832, 412, 1088, 668)), (3840, 2160, (1792, 952, 2048, 1208))],
@@ -166,6 +197,7 @@ def test_pan_64_frames_lowprec_crop(W, H, crop):
     say(f"case: {W}x{H} pan {T} frames, FP16/BF16/FP32 Gamma, crop {crop}")
     seq = wl.Sequence(W, H, seed)
     cone = OracleCone(seed, 1, crop, T, W, H)
+    twin = OracleCone(seed, 1, crop, T, W, H, round32=True)
     dts = {"f16": torch.float16, "bf16": torch.bfloat16, "f32": torch.float32}
     guides = {}
     prev_dev = v_prev = None
@@ -193,6 +225,7 @@ def test_pan_64_frames_lowprec_crop(W, H, crop):
             v_last_prev = v_prev
             fr_last = fr
         v_prev = cone.step(t, fr)
+        twin.step(t, fr)
         prev_dev = cur
     torch.cuda.synchronize()
     # implementation: the last frame against the storage-rounding oracle
@@ -203,6 +236,7 @@ def test_pan_64_frames_lowprec_crop(W, H, crop):
             f"flips {st['flips']}; {u}")
     # format error: free-running states against the FP64 oracle
     errs = {k: free_run_table(k, host_gamma(g.state), cone.gamma, crop) for k, g in guides.items()}
+    e_twin = free_run_table("twin", twin.gamma, cone.gamma, crop)
     # densities of one set of directions under each stored state and under the FP64 state
     v = O.OView(fr_last, fr_last["motion"], fr_last["disocc"])
     P = O.params(seed, frame=T - 1)
@@ -218,8 +252,7 @@ def test_pan_64_frames_lowprec_crop(W, H, crop):
     for k, lim in (("f16", 2e-3), ("bf16", 2e-2)):
         assert (errs[k]["k"] == 0).mean() > 0.99
         assert np.median(errs[k]["mu"]) <= lim and np.median(errs[k]["pi"]) <= lim, k
-    for name in ("mu", "sigma", "pi", "W"):
-        assert errs["f32"][name].max() <= TOL_EM_RUN, name
+    assert_free_run(errs["f32"], e_twin, f"{W}x{H} FP32 free run")
 
 
 def test_4k_spp4_gradient_fit_and_adjoint():
