@@ -45,7 +45,8 @@
  *     return PG_ERR_ARG (null required pointer, non-positive sizes, pitch <
  *     width, spp outside [1, 8], unknown dtype, forbidden aliasing);
  *     PG_ERR_UNSUPPORTED marks a valid request this build does not handle
- *     (radius other than 3, sizes beyond the 32-bit index range); a failed
+ *     (radius other than 3, width or height above 16384, a pitch of 2^24
+ *     or more, sizes beyond the 32-bit index range); a failed
  *     launch returns PG_ERR_HIP.  pg_last_error() then describes the error.
  *     Numeric trouble is never an error: a non-finite history starts a new
  *     model.

@@ -27,6 +27,25 @@ __device__ __forceinline__ float dot3(V3 a, V3 b) { return fmaf(a.z, b.z, fmaf(a
 // the per-sample paths use these instead wherever the argument is known to
 // be a normal number.
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+// x / d and y / d for d > 0 (and x, y at most a few times d) with one hardware
+// reciprocal, about 1.5 ulp each instead of a correctly rounded division's
+// ten instructions: d, and x and y with it, which leaves the quotients as
+// they are, is scaled by a power of two when it lies outside [2^-62, 2^62],
+// since the reciprocal flushes subnormal inputs and outputs.
+__device__ __forceinline__ void div2_pos(float x, float y, float d, float &qx, float &qy) {
+  const float s = d < 0x1p-62f ? 0x1p64f : (d > 0x1p62f ? 0x1p-64f : 1.0f);
+  const float r = __builtin_amdgcn_rcpf(d * s);
+  qx = (x * s) * r;
+  qy = (y * s) * r;
+}
+__device__ __forceinline__ float div_pos(float x, float d) {
+  float q, unused;
+  div2_pos(x, 0.0f, d, q, unused);
+  return q;
+}
+// Row offset y * pitch of a pixel: both below 2^24 (the library bounds the
+// sides and the pitch), so the full-rate 24-bit multiply gives it.
+__device__ __forceinline__ int row_off(int y, int pitch) { return (int)__umul24((uint32_t)y, (uint32_t)pitch); }
 // Element i of an array whose base is uniform across the wave, with i taken
 // as an unsigned 32-bit offset: the access then uses the scalar-base plus
 // vector-offset form instead of 64-bit address arithmetic in every lane.
@@ -191,11 +210,9 @@ struct Pixel {
   V3 wo;            // local view direction
   float alpha2;     // alpha^2
   float albedo_pi;  // albedo / pi
-  float a2_pi;      // alpha^2 / pi
-  float g1_wo_over_2wo;  // G1(wo) / (2 wo_z)
-  float f0, s_d, s_d_pi;
-  float one_m_f0;   // 1 - f0
-  float one_m_sd_q;  // (1 - s_d) / 4
+  float f0_g1, omf0_g1;  // f0 and 1 - f0 times G1(wo) / (2 pi wo_z)
+  float s_d, s_d_pi;
+  float one_m_sd_q;  // (1 - s_d) / (4 pi)
 };
 
 __device__ __forceinline__ float smith_g1(V3 v, float alpha2) {
@@ -209,8 +226,10 @@ __device__ __forceinline__ float smith_g1(V3 v, float alpha2) {
 //   p_ggx = D h_z/(4 wo.h) = alpha^2 |h|^4 h_z / (4 pi den^2 (wo.h))
 //   G1(wi) / wi_z          = 2 / (wi_z + q)
 //   f_spec = F D G1(wi) G1(wo) / (4 wi_z wo_z) = F D (G1(wo)/(2 wo_z)) / (wi_z + q)
-// and R = 1 / (den^2 (wo.h) (wi_z + q)) serves both denominators (the 1/4
-// of p_ggx rides on the constant (1 - s_d) / 4).
+// and R = 1 / (den^2 (wo.h) (wi_z + q)) serves both denominators; the 1/pi of
+// D rides on the pixel's G1(wo) / (2 pi wo_z), which also carries Schlick's
+// f0 and 1 - f0, and, with the 1/4 of p_ggx, on the constant
+// (1 - s_d) / (4 pi).
 __device__ __forceinline__ void brdf_eval(const Pixel &px, V3 wi, float &f, float &pdf) {
   const V3 h = V3{px.wo.x + wi.x, px.wo.y + wi.y, px.wo.z + wi.z};
   const float hh = dot3(h, h);
@@ -219,14 +238,14 @@ __device__ __forceinline__ void brdf_eval(const Pixel &px, V3 wi, float &f, floa
   const float wq = wi.z + q;
   const float woh_u = dot3(px.wo, h);  // |h| (wo . h_hat)
   const float R = __builtin_amdgcn_rcpf(den * den * woh_u * wq);
-  const float A = px.a2_pi * hh * hh;  // D den^2
-  const float pggx4 = A * h.z * wq * R;  // 4 p_ggx
+  const float A = px.alpha2 * hh * hh;  // pi D den^2
+  const float pggx4 = A * h.z * wq * R;  // 4 pi p_ggx
   pdf = fmaf(px.s_d_pi, wi.z, px.one_m_sd_q * pggx4);
   const float woh = woh_u * __builtin_amdgcn_rsqf(hh);
   const float m = 1.0f - woh;
   const float m2 = m * m;
-  const float F = fmaf(px.one_m_f0, m2 * m2 * m, px.f0);
-  f = fmaf(F * A * px.g1_wo_over_2wo, woh_u * R, px.albedo_pi);
+  const float Fg = fmaf(px.omf0_g1, m2 * m2 * m, px.f0_g1);  // F G1(wo) / (2 pi wo_z)
+  f = fmaf(Fg * A, woh_u * R, px.albedo_pi);
 }
 
 __device__ __forceinline__ float brdf_pdf_only(const Pixel &px, V3 wi) {
@@ -234,7 +253,7 @@ __device__ __forceinline__ float brdf_pdf_only(const Pixel &px, V3 wi) {
   const float hh = dot3(h, h);
   const float den = fmaf(px.alpha2, h.z * h.z, fmaf(h.x, h.x, h.y * h.y));
   const float R = frcp(den * den * dot3(px.wo, h));
-  const float pggx4 = px.a2_pi * hh * hh * h.z * R;  // 4 p_ggx
+  const float pggx4 = px.alpha2 * hh * hh * h.z * R;  // 4 pi p_ggx
   return fmaf(px.s_d_pi, wi.z, px.one_m_sd_q * pggx4);
 }
 

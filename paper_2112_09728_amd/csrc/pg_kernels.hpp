@@ -26,7 +26,7 @@ struct ParamsK {
   float stale_tau;
   // material constants derived on the host (FP32, as the device would round
   // them), so that kernels take them as uniform operands
-  float s_d_pi, one_m_f0, one_m_sd_q;  // s_d / pi, 1 - f0, (1 - s_d) / 4
+  float s_d_pi, one_m_f0, one_m_sd_q;  // s_d / pi, 1 - f0, (1 - s_d) / (4 pi)
 };
 
 struct SamplesK {
@@ -84,12 +84,11 @@ __device__ __forceinline__ Pixel make_pixel(const ParamsK &P, V3 n, V3 o, float 
   const float alpha = rough * rough;
   px.alpha2 = alpha * alpha;
   px.albedo_pi = albedo * kInvPi;
-  px.a2_pi = px.alpha2 * kInvPi;
-  px.g1_wo_over_2wo = smith_g1(px.wo, px.alpha2) * frcp(2.0f * px.wo.z);
-  px.f0 = P.f0;
+  const float g1 = smith_g1(px.wo, px.alpha2) * frcp(2.0f * kPi * px.wo.z);
+  px.f0_g1 = P.f0 * g1;
+  px.omf0_g1 = P.one_m_f0 * g1;
   px.s_d = P.s_d;
   px.s_d_pi = P.s_d_pi;
-  px.one_m_f0 = P.one_m_f0;
   px.one_m_sd_q = P.one_m_sd_q;
   return px;
 }
@@ -466,10 +465,10 @@ __device__ __forceinline__ void stage_records(const ViewK &v, const SamplesK &S,
     const int e = threadIdx.x + i * NT;
     // e < 2^13, so the float quotient floors exactly
     const int sy = (int)(((float)e + 0.5f) * (1.0f / SW));
-    const int sx = e - sy * SW;
+    const int sx = e - (int)__umul24((uint32_t)sy, (uint32_t)SW);
     const int gx = tx0 - kR + sx, gy = ty0 - kR + sy;
     in[i] = e < SA && gx >= 0 && gy >= 0 && gx < v.W && gy < v.H;
-    gi[i] = gy * v.pitch + gx;
+    gi[i] = row_off(gy, v.pitch) + gx;  // used only inside the image
   }
   for (int s = s0; s < S.spp; ++s) {
     // every load of this sample plane is issued before the first use
@@ -526,8 +525,8 @@ __device__ __forceinline__ void accum_to_unit(Accum &a, const LobeTerm &t) {
 
 struct EmCtx {
   Pixel px;
-  LobeTerm T;  // the lobe's Gaussian term in the centred square
-  float one_m_pi;
+  LobeTerm T;  // the lobe's Gaussian term
+  float pi;
 };
 
 // One training sample of a list (its staged record is never zero: lists
@@ -542,7 +541,7 @@ __device__ __forceinline__ void em_visit(const EmCtx &c, float4 r, Accum &a) {
   brdf_eval(c.px, l, f, pb);
   const float w = r.w * f * l.z;
   const float ga = lobe_eval(c.T, rx, ry);
-  const float gb = c.one_m_pi * pb;
+  const float gb = fmaf(-c.pi, pb, pb);  // (1 - pi) p_b, one rounding
   const float gam = ga * __builtin_amdgcn_rcpf(fmaxf(ga + gb, 1.17549435e-38f));
   a.B0 += w;
   const float vw = w * gam;
@@ -772,7 +771,7 @@ __device__ __forceinline__ void em_load(const ViewK &v, const SamplesK &S, const
 #pragma unroll
   for (int c = 0; c < 8; ++c) R.g[c] = 0.0f;
   if (x0 < v.W && y0 < v.H) {
-    const int idx0 = y0 * v.pitch + x0;
+    const int idx0 = row_off(y0, v.pitch) + x0;
     gamma_load(gamma, plane, idx0, R.g);
     R.alb = at(v.alb, idx0);
     R.rough = at(v.rough, idx0);
@@ -785,12 +784,12 @@ __device__ __forceinline__ void em_load(const ViewK &v, const SamplesK &S, const
     const int e = t + i * In::NT;
     // e < 2^13, so the float quotient floors exactly
     const int sy = (int)(((float)e + 0.5f) * (1.0f / In::SW));
-    const int sx = e - sy * In::SW;
+    const int sx = e - (int)__umul24((uint32_t)sy, (uint32_t)In::SW);
     const int gx = tx0 - kR + sx, gy = ty0 - kR + sy;
     R.st[i] = 0;
     R.px[i] = R.py[i] = R.pz[i] = R.pl[i] = R.pp[i] = 0.0f;
     if (e < In::SA && gx >= 0 && gy >= 0 && gx < v.W && gy < v.H) {
-      const int o = gy * v.pitch + gx;
+      const int o = row_off(gy, v.pitch) + gx;
       R.st[i] = at(S.strat, o);
       R.pp[i] = at(S.pb, o);
       R.px[i] = at(S.dir, o);
@@ -853,7 +852,7 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
     if (nc > 0) {
       const int lx = pa % TW, ly = pa / TW;
       len = build_list<TW, TH>(P, lds, ptab, list, pa, lx, ly, nc - S.spp, S.spp,
-                               (uint32_t)((ty0 + ly) * v.W + tx0 + lx));
+                               (uint32_t)(row_off(ty0 + ly, v.W) + tx0 + lx));
     }
     sh.work[pa] = (uint8_t)len;
     // E- and M-steps: pixels by decreasing list length
@@ -863,7 +862,7 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
   EmCtx c;
   float g[8];
   if (len > 0) {
-    const int idx = (ty0 + me / TW) * v.pitch + tx0 + me % TW;
+    const int idx = row_off(ty0 + me / TW, v.pitch) + tx0 + me % TW;
     gamma_load(gamma, plane, idx, g);
     c.px = make_pixel(P, load3(v.n, plane, idx), load3(v.o, plane, idx), at(v.rough, idx), at(v.alb, idx));
     if (STALE && !batch && g[7] >= 1.0f && stale_history(P, c.px, g, lds, list, me, len, NT)) gamma_reset(P, g);
@@ -872,7 +871,7 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
     const int iters = batch ? iterations : 1;
     for (int it = 0; it < iters; ++it) {
       c.T = lobe_term(gauss_setup(g[0], g[1], g[2], g[3], g[4], P.eps), g[5]);
-      c.one_m_pi = 1.0f - g[5];
+      c.pi = g[5];
       Accum a = {0, 0, 0, 0, 0, 0, 0};
       for (int j = 0; j < len; ++j) em_visit(c, list_record(lds, list[j * NT + me]), a);
       if (!(a.B0 > 0.0f)) break;
@@ -886,7 +885,8 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
         const float sn = eta * a.B1;
         const float sg = so + sn;
         if (sg > 0.0f && a.B1 > 0.0f) {
-          const float al = so / sg, be = sn / sg;
+          float al, be;
+          div2_pos(so, sn, sg, al, be);
           const float dx = g[0] - a.mx, dy = g[1] - a.my;
           const float ab = al * be;
           g[0] = fmaf(al, g[0], be * a.mx);
@@ -895,7 +895,7 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
           g[3] = fmaf(ab * dx, dy, fmaf(al, g[3], be * a.sxy));
           g[4] = fmaf(ab * dy, dy, fmaf(al, g[4], be * a.syy));
         }
-        float pn = sg / sw;
+        float pn = div_pos(sg, sw);  // sg <= sw: B1 <= B0 and pi <= 1
         if (!(P.flags & kNoClamp)) pn = fminf(fmaxf(pn, P.pi_lo), P.pi_hi);
         g[5] = pn;
         g[6] = sw;
@@ -908,7 +908,7 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
           g[3] = a.sxy;
           g[4] = a.syy;
         }
-        float pn = a.B1 / a.B0;
+        float pn = div_pos(a.B1, a.B0);
         if (!(P.flags & kNoClamp)) pn = fminf(fmaxf(pn, P.pi_lo), P.pi_hi);
         g[5] = pn;
       }
@@ -925,7 +925,7 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
     const bool changed = sh.work[t] > 0;
 #pragma unroll
     for (int ch = 0; ch < 8; ++ch) go[ch] = changed ? wb[ch * NT + t] : R.g[ch];
-    gamma_store(gamma, plane, y0 * v.pitch + x0, go);
+    gamma_store(gamma, plane, row_off(y0, v.pitch) + x0, go);
   }
 }
 

@@ -60,6 +60,8 @@ pg_status check_view(const pg_view *v, const char *name, bool need_albedo) {
   if (v->pitch < v->width) return fail(PG_ERR_ARG, "%s: pitch %d < width %d", name, v->pitch, v->width);
   if (v->width > kMaxDim || v->height > kMaxDim)
     return fail(PG_ERR_UNSUPPORTED, "%s: %dx%d exceeds %d", name, v->width, v->height, kMaxDim);
+  // kernels form row offsets y * pitch with 24-bit products
+  if (v->pitch >= (1 << 24)) return fail(PG_ERR_UNSUPPORTED, "%s: pitch %d is 2^24 or more", name, v->pitch);
   if ((int64_t)v->pitch * v->height * 8 * 3 >= ((int64_t)1 << 31))
     return fail(PG_ERR_UNSUPPORTED, "%s: pitch*height too large for 32-bit indexing", name);
   if (!v->normal || !v->view_dir || !v->depth || !v->roughness)
@@ -116,7 +118,7 @@ ParamsK to_k(const pg_params *p) {
   k.stale_tau = p->stale_tau;
   k.s_d_pi = p->s_diffuse * 0.318309886183790671538f;
   k.one_m_f0 = 1.0f - p->f0;
-  k.one_m_sd_q = 0.25f * (1.0f - p->s_diffuse);
+  k.one_m_sd_q = (1.0f - p->s_diffuse) * 0.0795774715459476678844f;  // / (4 pi)
   return k;
 }
 
