@@ -79,6 +79,9 @@ def test_argument_errors_before_launch():
                           None), pg.PG_ERR_ARG),
         (L.pg_reproject, (C.byref(P), C.byref(_view(w=20000)), C.byref(v), g, g2, None, None),
          pg.PG_ERR_UNSUPPORTED),
+        # row offsets are 24-bit products: a pitch of 2^24 is refused
+        (L.pg_reproject, (C.byref(P), C.byref(_view(h=1, pitch=1 << 24)), C.byref(_view(h=1, pitch=1 << 24)), g, g2,
+                          None, None), pg.PG_ERR_UNSUPPORTED),
         (L.pg_sample_mis, (C.byref(P), C.byref(v), g, C.byref(_samples(spp=0)), None), pg.PG_ERR_ARG),
         (L.pg_sample_mis, (C.byref(P), C.byref(v), g, C.byref(_samples(spp=9)), None), pg.PG_ERR_ARG),
         (L.pg_sample_mis, (C.byref(P), C.byref(v), pg.PgGamma(0, None), C.byref(s), None),
