@@ -747,12 +747,13 @@ struct EmShared {
 };
 
 // One thread's share of a training tile's inputs, held in registers while
-// the loads are in flight: the state of its pixel (natural order) and its
-// records of sample plane 0.
+// the loads are in flight: what decides its pixel's candidate count (epoch,
+// normal, view direction, roughness; natural order) and its records of
+// sample plane 0.
 template <int TW, int TH>
 struct EmInput {
   static constexpr int SW = TW + 2 * kR, SA = SW * (TH + 2 * kR), NT = TW * TH, IT = (SA + NT - 1) / NT;
-  float g[8], alb, rough;
+  float k, rough;
   V3 n, o;
   uint32_t st[IT];
   float px[IT], py[IT], pz[IT], pl[IT], pp[IT];
@@ -766,14 +767,11 @@ __device__ __forceinline__ void em_load(const ViewK &v, const SamplesK &S, const
   const int plane = v.H * v.pitch;
   const int t = threadIdx.x;
   const int x0 = tx0 + t % TW, y0 = ty0 + t / TW;
-  R.alb = R.rough = 0.0f;
+  R.k = R.rough = 0.0f;
   R.n = R.o = V3{0, 0, 0};
-#pragma unroll
-  for (int c = 0; c < 8; ++c) R.g[c] = 0.0f;
   if (x0 < v.W && y0 < v.H) {
     const int idx0 = row_off(y0, v.pitch) + x0;
-    gamma_load(gamma, plane, idx0, R.g);
-    R.alb = at(v.alb, idx0);
+    R.k = gamma_get(&at(gamma + 7 * plane, idx0), 7);
     R.rough = at(v.rough, idx0);
     R.n = load3(v.n, plane, idx0);
     R.o = load3(v.o, plane, idx0);
@@ -800,13 +798,13 @@ __device__ __forceinline__ void em_load(const ViewK &v, const SamplesK &S, const
   }
 }
 
-// One training tile.  Its inputs arrive in R (state of each pixel in natural
-// order, records of plane 0; further planes are staged here): stage the
-// records in LDS; sort the pixels by candidate count and build each pixel's
-// training list; sort them again by list length and run the E- and M-steps
-// (the lane of a pixel re-reads its state, which the natural-order load has
-// just brought into the caches); write the tile's Gamma back in natural order
-// through LDS (full cache lines).  Every thread of the block calls it and
+// One training tile.  Its inputs arrive in R (what decides each pixel's
+// candidate count, natural order; records of plane 0; further planes are
+// staged here): stage the records in LDS; sort the pixels by candidate count
+// and build each pixel's training list; sort them again by list length, load
+// each pixel's state and material in that order and run the E- and M-steps;
+// write the tile's Gamma back in natural order through LDS (full cache
+// lines).  Every thread of the block calls it and
 // none leaves early; a block that runs several tiles synchronises between
 // them (the write-back area overlaps the records).
 // Dynamic LDS: records [spp][SH][SW] float4, then lists [spp + 20][NT]
@@ -840,7 +838,7 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
   if (S.spp > 1) stage_records<TW, TH>(v, S, lds, tx0, ty0, 1);
   // the number of candidates of this lane's pixel (0 when it is not trained)
   int ncand = 0;
-  if (in_image && dot3(R.n, R.o) > 0.0f && R.rough >= P.rough_min) ncand = S.spp + n_picks(P, (int)R.g[7]);
+  if (in_image && dot3(R.n, R.o) > 0.0f && R.rough >= P.rough_min) ncand = S.spp + n_picks(P, (int)R.k);
   sh.work[t] = (uint8_t)ncand;
   __syncthreads();
   // lists: pixels by decreasing candidate count
@@ -861,9 +859,14 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
   const int len = sh.work[me];
   EmCtx c;
   float g[8];
+  // every pixel of the tile, trained or not, passes its state to the
+  // natural-order write-back through LDS (the loads run for the trained
+  // lanes of the wave anyway)
+  const int mex = tx0 + me % TW, mey = ty0 + me / TW;
+  const bool me_in = mex < v.W && mey < v.H;
+  const int idx = row_off(mey, v.pitch) + mex;
+  if (me_in) gamma_load(gamma, plane, idx, g);
   if (len > 0) {
-    const int idx = row_off(ty0 + me / TW, v.pitch) + tx0 + me % TW;
-    gamma_load(gamma, plane, idx, g);
     c.px = make_pixel(P, load3(v.n, plane, idx), load3(v.o, plane, idx), at(v.rough, idx), at(v.alb, idx));
     if (STALE && !batch && g[7] >= 1.0f && stale_history(P, c.px, g, lds, list, me, len, NT)) gamma_reset(P, g);
   }
@@ -915,16 +918,15 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
     }
   }
   __syncthreads();  // records and lists are no longer read
-  if (len > 0) {
+  if (me_in) {
 #pragma unroll
     for (int ch = 0; ch < 8; ++ch) wb[ch * NT + me] = g[ch];
   }
   __syncthreads();
   if (in_image) {
     float go[8];
-    const bool changed = sh.work[t] > 0;
 #pragma unroll
-    for (int ch = 0; ch < 8; ++ch) go[ch] = changed ? wb[ch * NT + t] : R.g[ch];
+    for (int ch = 0; ch < 8; ++ch) go[ch] = wb[ch * NT + t];
     gamma_store(gamma, plane, row_off(y0, v.pitch) + x0, go);
   }
 }
