@@ -167,7 +167,11 @@ struct Tile {
 };
 constexpr Tile kTiles[] = {{32, 8}, {16, 16}, {64, 4}, {32, 4}, {16, 8}, {64, 2}, {32, 16}, {64, 8}};
 
-Tile default_tile(int spp) { return spp <= 4 ? Tile{32, 8} : Tile{32, 4}; }
+// Default training tile per spp (1080p pan, EM per frame): 32x8 up to spp 4;
+// above, the staged records limit how many blocks share a CU's LDS, and the
+// shape that keeps the most waves resident wins: 16x16 at spp 5 (266 us
+// against 339 for 32x4), 16x8 at spp 6-8 (spp 8: 508 us against 726).
+Tile default_tile(int spp) { return spp <= 4 ? Tile{32, 8} : (spp == 5 ? Tile{16, 16} : Tile{16, 8}); }
 
 // Dynamic LDS of the training kernels: staged records [spp][h+6][w+6] float4,
 // the training lists [spp+20][w*h] uint16 and the pick table [48 spp] int16
