@@ -213,7 +213,7 @@ def main():
     ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     # keep the stream busy while the host enqueues frame 0, so that its
     # start event marks when the GPU reaches the launch, not when Python does
-    torch.cuda._sleep(200_000)
+    torch.cuda._sleep(2_000_000)
     for t in range(a.warmup):
         frame(t, ev0 if t == 0 else None)
     torch.cuda.synchronize()
