@@ -189,7 +189,9 @@ __device__ __forceinline__ float atan_4pi_unit(float t) {
 // avoids the cancellation of 1 - w_z; inside each of the four concentric
 // sectors the disk angle is atan of the ratio of the smaller to the larger of
 // w_x, w_y (the disk scaling cancels in that ratio).  Branch free.
-__device__ __forceinline__ void hemi2sq(V3 w, float &ux, float &uy) {
+// hemi2sq_c gives the point o = 2u - 1 of the centred square, hemi2sq the
+// point u of the unit square.
+__device__ __forceinline__ void hemi2sq_c(V3 w, float &ox, float &oy) {
   const float s2 = fmaf(w.x, w.x, w.y * w.y);
   const float rho = s2 > 0.0f ? s2 * __builtin_amdgcn_rsqf(s2 * (1.0f + w.z)) : 0.0f;
   const bool bigx = fabsf(w.x) > fabsf(w.y);
@@ -198,8 +200,14 @@ __device__ __forceinline__ void hemi2sq(V3 w, float &ux, float &uy) {
   const float t = den != 0.0f ? num * __builtin_amdgcn_rcpf(den) : 0.0f;
   const float r = copysignf(rho, den);
   const float o = r * atan_4pi_unit(t);
-  ux = fmaf(0.5f, bigx ? r : o, 0.5f);
-  uy = fmaf(0.5f, bigx ? o : r, 0.5f);
+  ox = bigx ? r : o;
+  oy = bigx ? o : r;
+}
+__device__ __forceinline__ void hemi2sq(V3 w, float &ux, float &uy) {
+  float ox, oy;
+  hemi2sq_c(w, ox, oy);
+  ux = fmaf(0.5f, ox, 0.5f);
+  uy = fmaf(0.5f, oy, 0.5f);
 }
 // ---------------------------------------------------------------------------
 // Synthetic material: Lambert + GGX (Walter et al., EGSR 2007) with Smith G1
@@ -288,20 +296,22 @@ __device__ __forceinline__ float gauss_q(const Gauss &g, float ux, float uy) {
 }
 
 // The weighted Gaussian term pi N(u) / (2 pi) of a lobe as the E-step
-// evaluates it, at a point given relative to the lobe's mean (r = u - mu,
-// exact near the mean):
+// evaluates it, at a point given relative to the lobe's mean, r = u - mu =
+// o/2 + h with h = 1/2 - mu, formed from the centred point o in one rounding
+// (h is exact for mu >= 1/4, within half an ulp of 1/2 below; the mean is
+// added back as 1/2 - h, exactly the centre the points were measured from):
 //   pi_norm exp2(-log2(e)/2 (z1^2 + z2^2)),  z1 = i11 rx,  z2 = i22 ry + c21 z1,
 // the whitening L^-1 (u - mu) with c21 = -l21 i22, and pi_norm =
 // pi / (4 pi^2 l11 l22).  (Folding sqrt(log2(e)/2) into i11 and i22 saves one
 // multiplication but rounds the scale twice and squares it, which the far
 // tail of a lobe carries into the weights: kept separate.)
 struct LobeTerm {
-  float mx, my, i11, i22, c21, pi_norm;
+  float hx, hy, i11, i22, c21, pi_norm;  // h = 1/2 - mu
 };
 __device__ __forceinline__ LobeTerm lobe_term(const Gauss &g, float pi) {
   LobeTerm t;
-  t.mx = g.mx;
-  t.my = g.my;
+  t.hx = 0.5f - g.mx;
+  t.hy = 0.5f - g.my;
   t.i11 = g.i11;
   t.i22 = g.i22;
   t.c21 = -g.l21 * g.i22;

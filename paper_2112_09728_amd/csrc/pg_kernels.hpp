@@ -519,8 +519,8 @@ struct Accum {
 
 // The mean of the points r = u - mu back to u (the scatter is the same).
 __device__ __forceinline__ void accum_to_unit(Accum &a, const LobeTerm &t) {
-  a.mx += t.mx;
-  a.my += t.my;
+  a.mx += 0.5f - t.hx;
+  a.my += 0.5f - t.hy;
 }
 
 struct EmCtx {
@@ -535,9 +535,9 @@ struct EmCtx {
 __device__ __forceinline__ void em_visit(const EmCtx &c, float4 r, Accum &a) {
   const V3 l = to_local(c.px.f, V3{r.x, r.y, r.z});
   if (l.z <= 0.0f) return;
-  float ux, uy, f, pb;
-  hemi2sq(l, ux, uy);
-  const float rx = ux - c.T.mx, ry = uy - c.T.my;
+  float ox, oy, f, pb;
+  hemi2sq_c(l, ox, oy);
+  const float rx = fmaf(0.5f, ox, c.T.hx), ry = fmaf(0.5f, oy, c.T.hy);
   brdf_eval(c.px, l, f, pb);
   const float w = r.w * f * l.z;
   const float ga = lobe_eval(c.T, rx, ry);
@@ -746,6 +746,16 @@ struct EmShared {
   uint8_t work[NT];  // per pixel: candidate count, then list length
 };
 
+// Dynamic LDS of the single-lobe training kernels: the records
+// [spp][h+6][w+6] float4, the lists [spp+20][w h] uint16 and the pick table
+// (the block's EmShared is static).  Keeping EmShared static measured 2% faster
+// than placing it after the dynamic area, where the records would start at
+// LDS address 0 and the list entries could serve as addresses directly.
+__host__ __device__ constexpr size_t em_lds_front(int tw, int th, int spp) {
+  return (size_t)(tw + 2 * kR) * (th + 2 * kR) * spp * 16 + (size_t)(spp + 20) * tw * th * 2 +
+         (size_t)pick_table_bytes(spp);
+}
+
 // One thread's share of a training tile's inputs, held in registers while
 // the loads are in flight: what decides its pixel's candidate count (epoch,
 // normal, view direction, roughness; natural order) and its records of
@@ -938,7 +948,7 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
 template <typename TG, int TW, int TH, bool STALE>
 __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(8))) void k_em(ParamsK P, ViewK v, SamplesK S, TG *__restrict__ gamma,
                                                int iterations, int batch, int tiles_x, int n_tiles) {
-  extern __shared__ float4 lds[];  // records, state and lists (see em_tile)
+  extern __shared__ float4 lds[];  // records, lists and the pick table (em_lds_front)
   __shared__ EmShared<TW * TH> sh;
   const int tile = xcd_tile(blockIdx.x, n_tiles);
   const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
@@ -1145,7 +1155,7 @@ __global__ __launch_bounds__(256) void k_rs_batched(const char *__restrict__ tab
 template <typename TG, int TW, int TH>
 __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TH == 2 ? 1 : 8))) void k_em_batched(const char *__restrict__ table, int dtype, int cls,
                                                        int spp_cap) {
-  extern __shared__ float4 lds[];
+  extern __shared__ float4 lds[];  // sized for spp_cap (em_lds_front)
   __shared__ EmShared<TW * TH> sh;
   const BatchHeader *hd = reinterpret_cast<const BatchHeader *>(table);
   if (hd->dtype != dtype || cls >= hd->n_classes) return;

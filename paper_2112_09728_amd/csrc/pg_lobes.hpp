@@ -296,15 +296,15 @@ __device__ __forceinline__ void lobes_visit(const LobesCtx<K> &c, float4 r, floa
   }
   const V3 l = to_local(c.px.f, wd);
   if (l.z <= 0.0f) return;
-  float ux, uy, f, pb;
-  hemi2sq(l, ux, uy);
+  float ox, oy, f, pb;
+  hemi2sq_c(l, ox, oy);
   brdf_eval(c.px, l, f, pb);
   const float w = r.w * f * l.z;
   float ga[K], rx[K], ry[K], D = c.one_m_tot * pb;
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    rx[j] = ux - c.T[j].mx;  // relative to lobe j's mean (see Accum)
-    ry[j] = uy - c.T[j].my;
+    rx[j] = fmaf(0.5f, ox, c.T[j].hx);  // relative to lobe j's mean (see Accum)
+    ry[j] = fmaf(0.5f, oy, c.T[j].hy);
     ga[j] = lobe_eval(c.T[j], rx[j], ry[j]);
     D += ga[j];
   }

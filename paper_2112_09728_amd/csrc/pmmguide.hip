@@ -173,13 +173,11 @@ constexpr Tile kTiles[] = {{32, 8}, {16, 16}, {64, 4}, {32, 4}, {16, 8}, {64, 2}
 // against 339 for 32x4), 16x8 at spp 6-8 (spp 8: 508 us against 726).
 Tile default_tile(int spp) { return spp <= 4 ? Tile{32, 8} : (spp == 5 ? Tile{16, 16} : Tile{16, 8}); }
 
-// Dynamic LDS of the training kernels: staged records [spp][h+6][w+6] float4,
-// the training lists [spp+20][w*h] uint16 and the pick table [48 spp] int16
-// (at least 8 floats per pixel, which the Gamma write-back reuses).
-size_t tile_lds(Tile t, int spp) {
-  return (size_t)(t.w + 2 * kR) * (t.h + 2 * kR) * spp * sizeof(float4) +
-         (size_t)(spp + 20) * t.w * t.h * sizeof(uint16_t) + (size_t)pick_table_bytes(spp);
-}
+// Dynamic LDS of the single-lobe training kernels: staged records
+// [spp][h+6][w+6] float4, the training lists [spp+20][w*h] uint16 and the
+// pick table [48 spp] int16 (at least 8 floats per pixel, which the Gamma
+// write-back reuses).
+size_t tile_lds(Tile t, int spp) { return em_lds_front(t.w, t.h, spp); }
 
 pg_status pick_tile(const pg_params *p, int spp, Tile &t) {
   if (p->tile_w == 0 && p->tile_h == 0) {
