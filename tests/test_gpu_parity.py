@@ -198,12 +198,13 @@ def _gpu_records(scene, g, p, spp, view):
 
 
 @pytest.mark.parametrize("W,H", [(64, 64), (67, 45), (1, 1), (5, 90)])
-@pytest.mark.parametrize("spp", [1, 4])
+@pytest.mark.parametrize("spp", [1, 4, 5, 8])
 @pytest.mark.parametrize("kreg", ["new", "random_new", "mixed", "saturated"])
 def test_em_parity_same_input(W, H, spp, kreg):
     """One EM update from the same state and the same records.  "new" is the
     state every model starts from (k = 0 after a reset); the other regimes are
-    random states, whose narrow lobes may sit far from the samples."""
+    random states, whose narrow lobes may sit far from the samples.  spp 5
+    and 8 run the library's default tiles above spp 4 (16x16, 16x8)."""
     say(f"case: em {W}x{H} spp {spp} {kreg}")
     seed = 5000 + W + 7 * H + spp
     scene = wl.make_scene(W, H, seed)
@@ -234,10 +235,10 @@ def test_em_parity_same_input(W, H, spp, kreg):
     say(f"  {st}  evidence-underflow pixels: {int(uf.sum())}")
 
 
-@pytest.mark.parametrize("spp", [1, 2])
+@pytest.mark.parametrize("spp", [1, 2, 8])
 def test_em_tile_shapes_bitwise_identical(spp):
-    """Every built training tile gives the same bits (at spp 2 the tiles whose
-    LDS would exceed 64 KiB are refused with PG_ERR_UNSUPPORTED)."""
+    """Every built training tile gives the same bits (above spp 1 the tiles
+    whose LDS would exceed 64 KiB are refused with PG_ERR_UNSUPPORTED)."""
     say(f"case: em tile invariance, spp {spp}")
     W, H, seed = 99, 61, 6001
     scene = wl.make_scene(W, H, seed)
@@ -257,7 +258,8 @@ def test_em_tile_shapes_bitwise_identical(spp):
         fitted.append((tw, th))
     torch.cuda.synchronize()
     say(f"  tiles run: {fitted}")
-    assert len(fitted) == 8 if spp == 1 else len(fitted) >= 6
+    assert fitted == [tl for tl in pg.guide.TILES if pg.guide._tile_lds(tl, spp) <= 64 * 1024]
+    assert len(fitted) == 8 if spp == 1 else len(fitted) >= 2
     for o in outs[1:]:
         assert (o.view(np.uint32) == outs[0].view(np.uint32)).all()
 
