@@ -523,6 +523,33 @@ __device__ __forceinline__ void accum_to_unit(Accum &a, const LobeTerm &t) {
   a.my += 0.5f - t.hy;
 }
 
+// Stepwise merge of one frame's E-step sums into the state (Sec. 3.2):
+// eta = 1/(k+1) and the evidence W; only ratios of evidences appear, so a
+// subnormal B1 is harmless.
+__device__ __forceinline__ void em_merge_online(const ParamsK &P, float g[8], const Accum &a) {
+  const float eta = frcp(g[7] + 1.0f);  // k + 1 in [1, kMax + 1]
+  const float sw = fmaf(1.0f - eta, g[6], eta * a.B0);
+  const float so = (1.0f - eta) * g[5] * g[6];
+  const float sn = eta * a.B1;
+  const float sg = so + sn;
+  if (sg > 0.0f && a.B1 > 0.0f) {
+    float al, be;
+    div2_pos(so, sn, sg, al, be);
+    const float dx = g[0] - a.mx, dy = g[1] - a.my;
+    const float ab = al * be;
+    g[0] = fmaf(al, g[0], be * a.mx);
+    g[1] = fmaf(al, g[1], be * a.my);
+    g[2] = fmaf(ab * dx, dx, fmaf(al, g[2], be * a.sxx));
+    g[3] = fmaf(ab * dx, dy, fmaf(al, g[3], be * a.sxy));
+    g[4] = fmaf(ab * dy, dy, fmaf(al, g[4], be * a.syy));
+  }
+  float pn = div_pos(sg, sw);  // sg <= sw: B1 <= B0 and pi <= 1
+  if (!(P.flags & kNoClamp)) pn = fminf(fmaxf(pn, P.pi_lo), P.pi_hi);
+  g[5] = pn;
+  g[6] = sw;
+  g[7] = fminf(g[7] + 1.0f, (float)P.k_max);
+}
+
 struct EmCtx {
   Pixel px;
   LobeTerm T;  // the lobe's Gaussian term
@@ -601,13 +628,39 @@ __device__ __forceinline__ void build_pick_table(int16_t *tab, int spp) {
   }
 }
 
+// The two-pass training tile (online EM at spp >= 2) holds the records of
+// the first ceil(spp/2) sample planes at a time; its dynamic LDS: those
+// records [PG][SA] float4, a validity bit for every candidate record of all
+// planes [spp SA] (bytes rounded up to 16), the lists [spp+20][w h] uint16,
+// the pick table and, per pixel, the list's entries in the first pass
+// [w h] uint8.
+__host__ __device__ constexpr int em2_planes(int spp) { return (spp + 1) >> 1; }
+__host__ __device__ constexpr size_t em2_bits_bytes(int tw, int th, int spp) {
+  return (((size_t)spp * (tw + 2 * kR) * (th + 2 * kR) + 31) / 32 * 4 + 15) & ~(size_t)15;
+}
+__host__ __device__ constexpr size_t em2_lds_front(int tw, int th, int spp) {
+  return (size_t)(tw + 2 * kR) * (th + 2 * kR) * em2_planes(spp) * 16 + em2_bits_bytes(tw, th, spp) +
+         (size_t)(spp + 20) * tw * th * 2 + (size_t)pick_table_bytes(spp) + (size_t)tw * th;
+}
+
+// Where a training tile's lists start in dynamic LDS (after the records, and
+// in the two-pass tile after the validity bits); the pick table follows the
+// lists.
+template <int TW, int TH, bool TWO>
+__device__ __forceinline__ uint16_t *em_lists(float4 *lds, int spp) {
+  constexpr int SA = (TW + 2 * kR) * (TH + 2 * kR);
+  if (TWO)
+    return reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(lds + em2_planes(spp) * SA) +
+                                        em2_bits_bytes(TW, TH, spp));
+  return reinterpret_cast<uint16_t *>(lds + spp * SA);
+}
+
 // The pick table of a training tile, at its place in dynamic LDS (called by
 // every thread before em_tile; em_tile's first barrier publishes it).
-template <int TW, int TH>
+template <int TW, int TH, bool TWO = false>
 __device__ __forceinline__ void build_em_pick_table(float4 *lds, int spp) {
   constexpr int SW = TW + 2 * kR, SA = SW * (TH + 2 * kR), NT = TW * TH;
-  build_pick_table<SA, SW>(reinterpret_cast<int16_t *>(reinterpret_cast<uint16_t *>(lds + spp * SA) + (spp + 20) * NT),
-                           spp);
+  build_pick_table<SA, SW>(reinterpret_cast<int16_t *>(em_lists<TW, TH, TWO>(lds, spp) + (spp + 20) * NT), spp);
 }
 
 // Number of neighbour picks N(k) = 5 + floor(15 (kMax - k) / kMax) (Sec. 4.2).
@@ -890,29 +943,7 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
       if (!(a.B0 > 0.0f)) break;
       accum_to_unit(a, c.T);
       if (!batch) {
-        // stepwise merge with eta = 1/(k+1) and evidence W; only ratios of
-        // evidences appear, so a subnormal B1 is harmless
-        const float eta = frcp(g[7] + 1.0f);  // k + 1 in [1, kMax + 1]
-        const float sw = fmaf(1.0f - eta, g[6], eta * a.B0);
-        const float so = (1.0f - eta) * g[5] * g[6];
-        const float sn = eta * a.B1;
-        const float sg = so + sn;
-        if (sg > 0.0f && a.B1 > 0.0f) {
-          float al, be;
-          div2_pos(so, sn, sg, al, be);
-          const float dx = g[0] - a.mx, dy = g[1] - a.my;
-          const float ab = al * be;
-          g[0] = fmaf(al, g[0], be * a.mx);
-          g[1] = fmaf(al, g[1], be * a.my);
-          g[2] = fmaf(ab * dx, dx, fmaf(al, g[2], be * a.sxx));
-          g[3] = fmaf(ab * dx, dy, fmaf(al, g[3], be * a.sxy));
-          g[4] = fmaf(ab * dy, dy, fmaf(al, g[4], be * a.syy));
-        }
-        float pn = div_pos(sg, sw);  // sg <= sw: B1 <= B0 and pi <= 1
-        if (!(P.flags & kNoClamp)) pn = fminf(fmaxf(pn, P.pi_lo), P.pi_hi);
-        g[5] = pn;
-        g[6] = sw;
-        g[7] = fminf(g[7] + 1.0f, (float)P.k_max);
+        em_merge_online(P, g, a);
       } else {
         if (a.B1 > 0.0f) {
           g[0] = a.mx;
@@ -941,21 +972,242 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
   }
 }
 
+// Two-pass training tile (online EM from spp 4).  Above spp 1 the staged
+// records of every sample plane fill the LDS and few blocks share a CU (at
+// spp 4 and 32x8, 3 blocks: VALU 53% busy; at spp 8, 18% occupancy).  Here
+// the records of the first PG = ceil(spp/2) planes are staged, with one
+// validity bit per candidate record of all planes; each pixel's list is built
+// once, as in em_tile, storing its entries of the first planes from the
+// front of its column and those of the last planes from the back; the E-step
+// runs over the first planes, the records area is restaged with the last
+// planes, and the same sums continue over them.  Each pass keeps the
+// training set's order, so the result does not depend on the tile shape.
+
+// Validity bits and (for planes below `pg`) records of sample planes
+// [s0, s1) of a tile; with `bits` false only records, placed at plane
+// s - s0.  Each thread's halo positions are computed once for all planes.
+template <int TW, int TH>
+__device__ __forceinline__ void stage2(const ViewK &v, const SamplesK &S, float4 *rec, uint32_t *vb, int tx0,
+                                       int ty0, int s0, int s1, int pg, bool bits) {
+  constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH, NT = TW * TH;
+  constexpr int IT = (SA + NT - 1) / NT;
+  const int plane = v.H * v.pitch;
+  const int splane = S.spp * plane;
+  int gi[IT];
+  bool in[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int e = threadIdx.x + i * NT;
+    // e < 2^13, so the float quotient floors exactly
+    const int sy = (int)(((float)e + 0.5f) * (1.0f / SW));
+    const int sx = e - (int)__umul24((uint32_t)sy, (uint32_t)SW);
+    const int gx = tx0 - kR + sx, gy = ty0 - kR + sy;
+    in[i] = e < SA && gx >= 0 && gy >= 0 && gx < v.W && gy < v.H;
+    gi[i] = row_off(gy, v.pitch) + gx;  // used only inside the image
+  }
+  for (int s = s0; s < s1; ++s) {
+    const bool keep_rec = !bits || s < pg;
+    const int rs = bits ? s : s - s0;  // plane index in the records area
+    // every load of this sample plane is issued before the first use
+    uint8_t st[IT];
+    float px[IT], py[IT], pz[IT], pl[IT], pp[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      st[i] = 0;
+      px[i] = py[i] = pz[i] = pl[i] = pp[i] = 0.0f;
+      if (in[i]) {
+        const int o = s * plane + gi[i];
+        st[i] = at(S.strat, o);
+        pp[i] = at(S.pb, o);
+        if (keep_rec) {
+          px[i] = at(S.dir, o);
+          py[i] = at(S.dir + splane, o);
+          pz[i] = at(S.dir + 2 * splane, o);
+          pl[i] = at(S.L, o);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int e = threadIdx.x + i * NT;
+      if (IT * NT == SA || e < SA) {
+        // a BRDF sample's density is a normal number (at least s_d cos/pi of
+        // a valid draw, or the GGX density of the drawn normal)
+        const bool ok = st[i] == 1 && pp[i] > 0.0f;
+        if (keep_rec)
+          rec[rs * SA + e] = ok ? make_float4(px[i], py[i], pz[i], pl[i] * frcp(fmaxf(pp[i], 1.17549435e-38f)))
+                                : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (bits && ok) {
+          const int b = s * SA + e;
+          atomicOr(&vb[b >> 5], 1u << (b & 31));
+        }
+      }
+    }
+  }
+}
+
+// Training list of one pixel for the two-pass tile: the same candidates in
+// the same order as build_list, kept by their validity bit; an entry is the
+// record's byte offset in its pass's records area, the first pass's entries
+// from the front of column `col`, the last pass's from the back.  Returns
+// the list length and the first pass's count in n0.
+template <int TW, int TH>
+__device__ __forceinline__ int build_list2(const ParamsK &P, const uint32_t *vb, const int16_t *ptab,
+                                           uint16_t *list, int col, int lx, int ly, int npick, int spp,
+                                           uint32_t pix, int &n0) {
+  constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH, NT = TW * TH;
+  const int cap = spp + 20;
+  const int split = em2_planes(spp) * SA;  // first record of the last pass
+  const uint32_t cs = (uint32_t)(kCand * spp);
+  const int own = (ly + kR) * SW + (lx + kR);
+  int a = 0, b = 0;  // entries of the first and of the last pass
+  auto put = [&](int e, bool ok) {
+    const bool last = e >= split;
+    const int slot = last ? cap - 1 - b : a;  // a rejected entry is overwritten by the next
+    list[slot * NT + col] = (uint16_t)((last ? e - split : e) << 4);
+    a += (ok && !last) ? 1 : 0;
+    b += (ok && last) ? 1 : 0;
+  };
+#pragma unroll
+  for (int s = 0; s < kMaxSpp; ++s)
+    if (s < spp) {
+      const int e = s * SA + own;
+      put(e, (vb[e >> 5] >> (e & 31)) & 1u);
+    }
+  for (int m0 = 0; m0 < npick; m0 += 8) {
+    const uint4 w4 = philox4x32_10(pix, P.frame, (1u << 16) | (uint32_t)(m0 >> 3), P.view, P.key0, P.key1);
+    int e[8];
+    uint32_t wv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      // the 16-bit field j of the four words, scaled to a code in [0, 48 spp)
+      const uint32_t word = (j >> 1) == 0 ? w4.x : (j >> 1) == 1 ? w4.y : (j >> 1) == 2 ? w4.z : w4.w;
+      const uint32_t h = (j & 1) ? (word >> 16) : (word & 0xFFFFu);
+      e[j] = own + ptab[__umul24(h, cs) >> 16];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) wv[j] = vb[e[j] >> 5];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (m0 + j < npick) put(e[j], (wv[j] >> (e[j] & 31)) & 1u);
+  }
+  n0 = a;
+  return a + b;
+}
+
+template <typename TG, int TW, int TH>
+__device__ __forceinline__ void em_tile2(const ParamsK &P, const ViewK &v, const SamplesK &S, TG *gamma, int tx0,
+                                         int ty0, int rot, float4 *lds, EmShared<TW * TH> &sh,
+                                         const EmInput<TW, TH> &R) {
+  constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH, NT = TW * TH, IT = EmInput<TW, TH>::IT;
+  const int spp = S.spp, pg = em2_planes(spp), cap = spp + 20;
+  float4 *rec = lds;
+  uint32_t *vb = reinterpret_cast<uint32_t *>(lds + pg * SA);
+  const int nvb = (int)(em2_bits_bytes(TW, TH, spp) / 4);
+  uint16_t *list = em_lists<TW, TH, true>(lds, spp);
+  const int16_t *ptab = reinterpret_cast<const int16_t *>(list + cap * NT);
+  uint8_t *work0 = reinterpret_cast<uint8_t *>(list + cap * NT) + pick_table_bytes(spp);
+  float *wb = reinterpret_cast<float *>(lds);  // write-back area (records, bits, lists: all dead by then)
+  const int plane = v.H * v.pitch;
+  const int t = threadIdx.x;
+  const int x0 = tx0 + t % TW, y0 = ty0 + t / TW;
+  const bool in_image = x0 < v.W && y0 < v.H;
+  if (t < 2 * kMaxLen) (&sh.cnt[0][0])[t] = 0;
+  for (int w = t; w < nvb; w += NT) vb[w] = 0u;
+  __syncthreads();  // the bits are zero before they are set
+  // plane 0 from the registers, then the other planes
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int e = t + i * NT;
+    if (IT * NT == SA || e < SA) {
+      const bool ok = R.st[i] == 1 && R.pp[i] > 0.0f;
+      rec[e] = ok ? make_float4(R.px[i], R.py[i], R.pz[i], R.pl[i] * frcp(fmaxf(R.pp[i], 1.17549435e-38f)))
+                  : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (ok) atomicOr(&vb[e >> 5], 1u << (e & 31));
+    }
+  }
+  stage2<TW, TH>(v, S, rec, vb, tx0, ty0, 1, spp, pg, true);
+  int ncand = 0;
+  if (in_image && dot3(R.n, R.o) > 0.0f && R.rough >= P.rough_min) ncand = spp + n_picks(P, (int)R.k);
+  sh.work[t] = (uint8_t)ncand;
+  __syncthreads();
+  int me;
+  {
+    const int pa = balance<NT>(ncand, t, sh.cnt[0], sh.perm, rot);
+    const int nc = sh.work[pa];
+    int len = 0, n0 = 0;
+    if (nc > 0) {
+      const int lx = pa % TW, ly = pa / TW;
+      len = build_list2<TW, TH>(P, vb, ptab, list, pa, lx, ly, nc - spp, spp,
+                                (uint32_t)(row_off(ty0 + ly, v.W) + tx0 + lx), n0);
+    }
+    sh.work[pa] = (uint8_t)len;
+    work0[pa] = (uint8_t)n0;
+    me = balance<NT>(len, pa, sh.cnt[1], sh.perm, rot + 1);
+  }
+  const int len = sh.work[me], n0 = work0[me];
+  float g[8];
+  const int mex = tx0 + me % TW, mey = ty0 + me / TW;
+  const bool me_in = mex < v.W && mey < v.H;
+  const int idx = row_off(mey, v.pitch) + mex;
+  if (me_in) gamma_load(gamma, plane, idx, g);
+  Accum a = {0, 0, 0, 0, 0, 0, 0};
+  // the pixel's context is built for each pass (its loads hit the caches):
+  // across the restaging only the sums and the state stay in registers
+  if (len > 0) {
+    EmCtx c;
+    c.px = make_pixel(P, load3(v.n, plane, idx), load3(v.o, plane, idx), at(v.rough, idx), at(v.alb, idx));
+    c.T = lobe_term(gauss_setup(g[0], g[1], g[2], g[3], g[4], P.eps), g[5]);
+    c.pi = g[5];
+    for (int j = 0; j < n0; ++j) em_visit(c, list_record(rec, list[j * NT + me]), a);
+  }
+  __syncthreads();  // the first planes' records are no longer read
+  stage2<TW, TH>(v, S, rec, vb, tx0, ty0, pg, spp, 0, false);
+  __syncthreads();
+  if (len > 0) {
+    EmCtx c;
+    c.px = make_pixel(P, load3(v.n, plane, idx), load3(v.o, plane, idx), at(v.rough, idx), at(v.alb, idx));
+    c.T = lobe_term(gauss_setup(g[0], g[1], g[2], g[3], g[4], P.eps), g[5]);
+    c.pi = g[5];
+    for (int j = cap - 1; j >= cap - (len - n0); --j) em_visit(c, list_record(rec, list[j * NT + me]), a);
+    if (a.B0 > 0.0f) {  // otherwise no weight: the model stays as it is
+      accum_to_unit(a, c.T);
+      em_merge_online(P, g, a);
+    }
+  }
+  __syncthreads();  // records and lists are no longer read
+  if (me_in) {
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) wb[ch * NT + me] = g[ch];
+  }
+  __syncthreads();
+  if (in_image) {
+    float go[8];
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) go[ch] = wb[ch * NT + t];
+    gamma_store(gamma, plane, row_off(y0, v.pitch) + x0, go);
+  }
+}
+
 // One tile per block (blocks are mapped to XCD bands by xcd_tile); with the
 // LDS and registers of a tile, several blocks share each CU, which hides the
 // loads of one block behind the arithmetic of the others better than a
 // persistent loop with register prefetch.
-template <typename TG, int TW, int TH, bool STALE>
+// TWO: the two-pass tile (online EM above spp 1; em2_lds_front).
+template <typename TG, int TW, int TH, bool STALE, bool TWO = false>
 __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(8))) void k_em(ParamsK P, ViewK v, SamplesK S, TG *__restrict__ gamma,
                                                int iterations, int batch, int tiles_x, int n_tiles) {
-  extern __shared__ float4 lds[];  // records, lists and the pick table (em_lds_front)
+  extern __shared__ float4 lds[];  // records, lists and the pick table (em_lds_front, em2_lds_front)
   __shared__ EmShared<TW * TH> sh;
   const int tile = xcd_tile(blockIdx.x, n_tiles);
   const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
-  build_em_pick_table<TW, TH>(lds, S.spp);  // before the loads: fewer live registers
+  build_em_pick_table<TW, TH, TWO>(lds, S.spp);  // before the loads: fewer live registers
   EmInput<TW, TH> R;
   em_load(v, S, gamma, tx0, ty0, R);
-  em_tile<TG, TW, TH, STALE>(P, v, S, gamma, iterations, batch, tx0, ty0, (int)blockIdx.x, lds, sh, R);
+  if (TWO)
+    em_tile2<TG, TW, TH>(P, v, S, gamma, tx0, ty0, (int)blockIdx.x, lds, sh, R);
+  else
+    em_tile<TG, TW, TH, STALE>(P, v, S, gamma, iterations, batch, tx0, ty0, (int)blockIdx.x, lds, sh, R);
 }
 
 // ---------------------------------------------------------------------------
@@ -1152,10 +1404,10 @@ __global__ __launch_bounds__(256) void k_rs_batched(const char *__restrict__ tab
 // VGPRs).  `spp_cap` is the spp the dynamic LDS was sized for; a table whose
 // class differs from the launch (tile, spp, dtype, or more tiles than the
 // grid) is not processed.
-template <typename TG, int TW, int TH>
+template <typename TG, int TW, int TH, bool TWO>
 __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TH == 2 ? 1 : 8))) void k_em_batched(const char *__restrict__ table, int dtype, int cls,
                                                        int spp_cap) {
-  extern __shared__ float4 lds[];  // sized for spp_cap (em_lds_front)
+  extern __shared__ float4 lds[];  // sized for spp_cap (em_lds_front, em2_lds_front)
   __shared__ EmShared<TW * TH> sh;
   const BatchHeader *hd = reinterpret_cast<const BatchHeader *>(table);
   if (hd->dtype != dtype || cls >= hd->n_classes) return;
@@ -1172,10 +1424,13 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TH == 2 
   const int l = t - bv.em_begin;
   const int tx0 = (l % bv.em_tiles_x) * TW, ty0 = (l / bv.em_tiles_x) * TH;
   const ParamsK P = batch_params(hd->base, bv);
-  build_em_pick_table<TW, TH>(lds, bv.S.spp);
+  build_em_pick_table<TW, TH, TWO>(lds, bv.S.spp);
   EmInput<TW, TH> R;
   em_load(bv.cur, bv.S, (const TG *)bv.gout, tx0, ty0, R);
-  em_tile<TG, TW, TH>(P, bv.cur, bv.S, (TG *)bv.gout, 1, 0, tx0, ty0, (int)blockIdx.x, lds, sh, R);
+  if (TWO)
+    em_tile2<TG, TW, TH>(P, bv.cur, bv.S, (TG *)bv.gout, tx0, ty0, (int)blockIdx.x, lds, sh, R);
+  else
+    em_tile<TG, TW, TH>(P, bv.cur, bv.S, (TG *)bv.gout, 1, 0, tx0, ty0, (int)blockIdx.x, lds, sh, R);
 }
 
 // Philox words for given counters (diagnostic entry).

@@ -167,21 +167,39 @@ struct Tile {
 };
 constexpr Tile kTiles[] = {{32, 8}, {16, 16}, {64, 4}, {32, 4}, {16, 8}, {64, 2}, {32, 16}, {64, 8}};
 
-// Default training tile per spp (1080p pan, EM per frame): 32x8 up to spp 4;
-// above, the staged records limit how many blocks share a CU's LDS, and the
-// shape that keeps the most waves resident wins: 16x16 at spp 5 (266 us
-// against 339 for 32x4), 16x8 at spp 6-8 (spp 8: 508 us against 726).
-Tile default_tile(int spp) { return spp <= 4 ? Tile{32, 8} : (spp == 5 ? Tile{16, 16} : Tile{16, 8}); }
+// Default training tile per spp (1080p pan, EM per frame).  The two-pass
+// tile (online EM from spp 4) runs best at 16x16 (spp 4 230 us against 239
+// at 32x8; spp 6 295 against 356; spp 8 382 against 401 and 437 at 16x8).
+// The single-pass tile (up to spp 3, and batch EM or the stale test above):
+// 32x8 up to spp 4; above, the staged records limit how many blocks share a
+// CU's LDS, and the shape that keeps the most waves resident wins: 16x16 at
+// spp 5 (266 us against 339 for 32x4), 16x8 at spp 6-8 (spp 8: 508 us
+// against 726).
+Tile default_tile(int spp, bool two) {
+  if (two) return Tile{16, 16};
+  return spp <= 4 ? Tile{32, 8} : (spp == 5 ? Tile{16, 16} : Tile{16, 8});
+}
 
 // Dynamic LDS of the single-lobe training kernels: staged records
 // [spp][h+6][w+6] float4, the training lists [spp+20][w*h] uint16 and the
 // pick table [48 spp] int16 (at least 8 floats per pixel, which the Gamma
-// write-back reuses).
-size_t tile_lds(Tile t, int spp) { return em_lds_front(t.w, t.h, spp); }
+// write-back reuses); the two-pass tile (online EM at spp >= 2, `two`)
+// stages half the planes at a time plus a validity bit per record.
+size_t tile_lds(Tile t, int spp, bool two) {
+  return two ? em2_lds_front(t.w, t.h, spp) : em_lds_front(t.w, t.h, spp);
+}
 
-pg_status pick_tile(const pg_params *p, int spp, Tile &t) {
+// Whether a training launch takes the two-pass tile: online EM from spp 4
+// without the stale-history test (batch EM revisits the whole list every
+// iteration, and the test reads it before the E-step).  At 1080p EM per
+// frame: spp 8 382 us (16x16) against 503 single-pass, spp 4 230 against
+// 246; at spp 2 the single-pass tile already keeps 5 blocks per CU and the
+// second pass costs more than it gains (182 against 157 us).
+bool em_two_pass(int spp, int batch, uint32_t flags) { return spp >= 4 && !batch && !(flags & PG_STALE_RESET); }
+
+pg_status pick_tile(const pg_params *p, int spp, Tile &t, bool two = false) {
   if (p->tile_w == 0 && p->tile_h == 0) {
-    t = default_tile(spp);
+    t = default_tile(spp, two);
   } else {
     bool found = false;
     for (const Tile &c : kTiles)
@@ -189,9 +207,9 @@ pg_status pick_tile(const pg_params *p, int spp, Tile &t) {
     if (!found) return fail(PG_ERR_UNSUPPORTED, "tile %dx%d is not built", p->tile_w, p->tile_h);
     t = Tile{p->tile_w, p->tile_h};
   }
-  if (tile_lds(t, spp) > 64 * 1024)
+  if (tile_lds(t, spp, two) > 64 * 1024)
     return fail(PG_ERR_UNSUPPORTED, "tile %dx%d with spp %d needs %zu B of LDS (> 64 KiB)", t.w, t.h, spp,
-                tile_lds(t, spp));
+                tile_lds(t, spp, two));
   return PG_OK;
 }
 
@@ -200,8 +218,12 @@ pg_status launch_em_t(const ParamsK &P, const ViewK &v, const SamplesK &S, TG *g
                       hipStream_t st) {
   const int tx = (v.W + TW - 1) / TW, ty = (v.H + TH - 1) / TH;
   const int n = tx * ty;
-  const size_t lds = tile_lds(Tile{TW, TH}, S.spp);
-  if ((P.flags & kStaleReset) && !batch)
+  const bool two = em_two_pass(S.spp, batch, P.flags);
+  const size_t lds = tile_lds(Tile{TW, TH}, S.spp, two);
+  if (two)
+    hipLaunchKernelGGL((k_em<TG, TW, TH, false, true>), dim3(n), dim3(TW * TH), lds, st, P, v, S, g, iters, batch,
+                       tx, n);
+  else if ((P.flags & kStaleReset) && !batch)
     hipLaunchKernelGGL((k_em<TG, TW, TH, true>), dim3(n), dim3(TW * TH), lds, st, P, v, S, g, iters, batch, tx, n);
   else
     hipLaunchKernelGGL((k_em<TG, TW, TH, false>), dim3(n), dim3(TW * TH), lds, st, P, v, S, g, iters, batch, tx, n);
@@ -354,11 +376,16 @@ BatchViewK to_batch(const pg_batch_view &b, int rs_begin, int em_begin, Tile t) 
 
 template <typename TG, int TW, int TH>
 pg_status launch_em_batched_t(const void *table, int dtype, int cls, int spp, int n_tiles, hipStream_t st) {
-  const size_t lds = tile_lds(Tile{TW, TH}, spp);
+  const bool two = em_two_pass(spp, 0, 0);  // the batched frame runs online EM
+  const size_t lds = tile_lds(Tile{TW, TH}, spp, two);
   if (n_tiles < 1) return PG_OK;
   // one tile per block, like k_em (the class's tile count is fixed by its views)
-  hipLaunchKernelGGL((k_em_batched<TG, TW, TH>), dim3(n_tiles), dim3(TW * TH), lds, st, (const char *)table, dtype,
-                     cls, spp);
+  if (two)
+    hipLaunchKernelGGL((k_em_batched<TG, TW, TH, true>), dim3(n_tiles), dim3(TW * TH), lds, st, (const char *)table,
+                       dtype, cls, spp);
+  else
+    hipLaunchKernelGGL((k_em_batched<TG, TW, TH, false>), dim3(n_tiles), dim3(TW * TH), lds, st, (const char *)table,
+                       dtype, cls, spp);
   return PG_OK;
 }
 
@@ -379,17 +406,18 @@ pg_status launch_em_batched(const BatchClass &c, const void *table, int dtype, i
 // Training tile of a class of the batch: the requested one where its LDS
 // fits that spp, else the default for that spp.
 pg_status class_tile(const pg_params *p, int spp, Tile &t) {
+  const bool two = em_two_pass(spp, 0, 0);  // the batched frame runs online EM
   if (p->tile_w == 0 && p->tile_h == 0) {
-    t = default_tile(spp);
+    t = default_tile(spp, two);
     return PG_OK;
   }
-  pg_status st = pick_tile(p, spp, t);
+  pg_status st = pick_tile(p, spp, t, em_two_pass(spp, 0, 0));
   if (st == PG_OK) return st;
   bool built = false;
   for (const Tile &c : kTiles)
     if (c.w == p->tile_w && c.h == p->tile_h) built = true;
   if (!built) return st;  // an unknown shape stays an error
-  t = default_tile(spp);
+  t = default_tile(spp, two);
   return ok();
 }
 
@@ -544,7 +572,7 @@ pg_status pg_em_update(const pg_params *p, const pg_view *v, const pg_samples *i
   if (iterations < 1 || (!batch && iterations != 1) || iterations > 1000)
     return fail(PG_ERR_ARG, "iterations %d invalid (1 without PG_EM_BATCH, 1..1000 with it)", iterations);
   Tile t;
-  if ((st = pick_tile(p, in->spp, t))) return st;
+  if ((st = pick_tile(p, in->spp, t, em_two_pass(in->spp, batch, p->flags)))) return st;
   const ParamsK P = to_k(p);
   const ViewK V = to_k(v);
   const SamplesK S = to_k(in);

@@ -22,10 +22,17 @@ TILES = ((32, 8), (16, 16), (64, 4), (32, 4), (16, 8), (64, 2), (32, 16), (64, 8
 
 
 def _tile_lds(tile, spp: int) -> int:
-    """Dynamic LDS bytes of a training tile (records with the 3-pixel halo,
-    the training lists and the pick table), as the library sizes it."""
+    """Dynamic LDS bytes of a training tile for online EM, as the library
+    sizes it: the records with the 3-pixel halo (from spp 4 half the sample
+    planes at a time, with a validity bit per record of all planes and a
+    byte per pixel), the training lists and the pick table."""
     w, h = tile
-    return (w + 6) * (h + 6) * spp * 16 + (spp + 20) * w * h * 2 + ((48 * spp * 2 + 15) & ~15)
+    sa = (w + 6) * (h + 6)
+    lists = (spp + 20) * w * h * 2 + ((48 * spp * 2 + 15) & ~15)
+    if spp < 4:
+        return sa * spp * 16 + lists
+    bits = ((spp * sa + 31) // 32 * 4 + 15) & ~15
+    return sa * ((spp + 1) // 2) * 16 + bits + lists + w * h
 
 
 class DeviceFrame:

@@ -247,8 +247,8 @@ def test_batch_pack_layout_and_tile_counts():
     assert (n, dtype, n_classes, magic) == (5, pg.PG_F32, 4, 0x31424750)
     assert rs == sum(-(-w // 64) * -(-h // 4) for w, h, _ in sizes)
 
-    def tiles(w, h, spp):  # 32x8 needs more than 64 KiB of LDS at spp 8: the default 16x8 there
-        tw, th = (32, 8) if spp <= 4 else ((16, 16) if spp == 5 else (16, 8))
+    def tiles(w, h, spp):  # the requested 32x8 fits every spp in the batched frame's two-pass tile
+        tw, th = 32, 8
         return -(-w // tw) * -(-h // th)
     assert em == sum(tiles(*v) for v in sizes)
     assert pg.batch_table_bytes(0) == 0

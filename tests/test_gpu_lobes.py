@@ -222,16 +222,21 @@ def test_pdf_parity(K):
     assert np.quantile(r[pos], 0.999) <= TOL_PDF and r[pos].max() <= 1e-3, (np.quantile(r[pos], 0.999), r.max())
 
 
-def test_one_lobe_matches_the_single_lobe_kernels():
+@pytest.mark.parametrize("spp", [2, 4])
+def test_one_lobe_matches_the_single_lobe_kernels(spp):
     """K = 1 through the K-lobe kernels against the single-lobe kernels on the
     same inputs: the same reprojected state, strategies and directions bit
     for bit, densities within 1e-5 (99.9%; the single-lobe kernel takes each
     strategy's density in its sample space), and after the update the same
-    epochs and every channel within 1e-6 (mu and pi absolute, Sigma relative
-    to its trace, W relative: the two kernels are contracted into fused
-    multiply-adds in different places, and the weight clamp is a scaling)."""
-    W, H, spp, seed = 93, 50, 2, 13700
-    say("case: K = 1 against the single-lobe kernels")
+    epochs and every channel within 1e-6 at spp 2 (mu and pi absolute, Sigma
+    relative to its trace, W relative: the two kernels are contracted into
+    fused multiply-adds in different places, and the weight clamp is a
+    scaling).  From spp 4 the single-lobe kernel visits the samples of the
+    last half of the sample planes after those of the first (its two-pass
+    tile) while the K-lobe kernel keeps the training set's order, so the FP32
+    sums round differently: within the one-step tolerance TOL_EM_FRAME."""
+    W, H, seed = 93, 50, 13700 + spp
+    say(f"case: K = 1 against the single-lobe kernels, spp {spp}")
     scene = wl.make_scene(W, H, seed)
     rng = np.random.default_rng(seed)
     g_prev = random_lobes(1, H, W, rng, k_lo=0)
@@ -257,7 +262,7 @@ def test_one_lobe_matches_the_single_lobe_kernels():
     pg.em_update_lobes(p, 1, cur, a_s, b_g)
     torch.cuda.synchronize()
     ga, gb = host(a_g), host(b_g)
-    e = assert_gamma_close(gb, ga, 1e-6, what="K = 1 against the single lobe")
+    e = assert_gamma_close(gb, ga, 1e-6 if spp < 4 else TOL_EM_FRAME, what="K = 1 against the single lobe")
     say(f"  after the update: {e}")
 
 

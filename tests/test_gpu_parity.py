@@ -235,7 +235,7 @@ def test_em_parity_same_input(W, H, spp, kreg):
     say(f"  {st}  evidence-underflow pixels: {int(uf.sum())}")
 
 
-@pytest.mark.parametrize("spp", [1, 2, 8])
+@pytest.mark.parametrize("spp", [1, 2, 4, 8])
 def test_em_tile_shapes_bitwise_identical(spp):
     """Every built training tile gives the same bits (above spp 1 the tiles
     whose LDS would exceed 64 KiB are refused with PG_ERR_UNSUPPORTED)."""

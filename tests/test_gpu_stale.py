@@ -82,16 +82,26 @@ def test_stale_reset_parity(tau):
     say(f"  EM {e}")
 
 
-def test_stale_reset_with_infinite_threshold_is_the_default_update():
-    W, H, spp, seed = 67, 45, 2, 9500
-    say("case: stale reset, tau = +inf")
+@pytest.mark.parametrize("spp", [2, 4])
+def test_stale_reset_with_infinite_threshold_is_the_default_update(spp):
+    """A threshold that never fires leaves the update as it is: bit for bit
+    below spp 4.  From spp 4 the default update runs the two-pass training tile,
+    which visits the samples of the last half of the sample planes after the
+    first, while the stale test needs every record staged at once and keeps
+    the training set's order: the FP32 sums round differently, within the
+    one-step tolerance, and the epochs agree."""
+    W, H, seed = 67, 45, 9500 + spp
+    say(f"case: stale reset, tau = +inf, spp {spp}")
     sc, v, rec, g = _setup(W, H, spp, seed)
     view, s = gpu_view(sc), _gpu_samples(rec)
     a, b = dev(g), dev(g)
     pg.em_update(pg.params(seed, frame=3), view, s, a)
     pg.em_update(pg.params(seed, frame=3, flags=pg.PG_STALE_RESET, stale_tau=1e30), view, s, b)
     torch.cuda.synchronize()
-    assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+    if spp < 4:
+        assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+    else:
+        assert_gamma_close(host(b), host(a).astype(np.float64), TOL_EM_FRAME, what="tau = +inf against the default")
 
 
 def test_recovery_after_a_light_moves():
