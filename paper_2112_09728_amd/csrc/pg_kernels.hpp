@@ -628,7 +628,7 @@ __device__ __forceinline__ void build_pick_table(int16_t *tab, int spp) {
   }
 }
 
-// The two-pass training tile (online EM at spp >= 2) holds the records of
+// The two-pass training tile (online EM from spp 4) holds the records of
 // the first ceil(spp/2) sample planes at a time; its dynamic LDS: those
 // records [PG][SA] float4, a validity bit for every candidate record of all
 // planes [spp SA] (bytes rounded up to 16), the lists [spp+20][w h] uint16,

@@ -183,7 +183,7 @@ Tile default_tile(int spp, bool two) {
 // Dynamic LDS of the single-lobe training kernels: staged records
 // [spp][h+6][w+6] float4, the training lists [spp+20][w*h] uint16 and the
 // pick table [48 spp] int16 (at least 8 floats per pixel, which the Gamma
-// write-back reuses); the two-pass tile (online EM at spp >= 2, `two`)
+// write-back reuses); the two-pass tile (online EM from spp 4, `two`)
 // stages half the planes at a time plus a validity bit per record.
 size_t tile_lds(Tile t, int spp, bool two) {
   return two ? em2_lds_front(t.w, t.h, spp) : em_lds_front(t.w, t.h, spp);
