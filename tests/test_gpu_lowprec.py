@@ -26,10 +26,12 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+@pytest.mark.parametrize("spp", [1, 4, 8])
 @pytest.mark.parametrize("fmt", ["f16", "bf16"])
-def test_lowprec_frames_match_storage_rounding_oracle(fmt):
-    say(f"case: {fmt} frames")
-    W, H, spp, seed = 80, 56, 1, wl.SEED_BASE + 3
+def test_lowprec_frames_match_storage_rounding_oracle(fmt, spp):
+    """spp 4 and 8 train with the two-pass tile."""
+    say(f"case: {fmt} frames spp {spp}")
+    W, H, seed = 80, 56, wl.SEED_BASE + 3
     seq = wl.Sequence(W, H, seed)
     fr = seq.frame(0)
     dt = FMT[fmt][0]
