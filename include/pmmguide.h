@@ -201,7 +201,11 @@ pg_status pg_light_field(const pg_lights *lights, const pg_view *v, const uint8_
  * gamma of the Gaussian against the BRDF under the model's pi.  M-step:
  * the batch mean/covariance merged with the state by eta = 1/(k+1) and the
  * evidence W; pi = clamp(.., pi_lo, pi_hi) unless PG_NO_CLAMP; k += 1 (at
- * most kMax).  An empty batch leaves the pixel unchanged.
+ * most kMax).  An empty batch leaves the pixel unchanged.  The E-step sums
+ * the training set in the order above, except for the online update from
+ * spp 4, which sums the members drawn from sample planes below ceil(spp/2)
+ * first and then the rest, each part in that order (a different rounding
+ * order of the same sums; the tile never changes the result).
  * With PG_EM_BATCH in p->flags, `iterations` rounds of plain batch EM run on
  * the same training set (mu, Sigma, pi replaced; W and k kept); otherwise
  * `iterations` must be 1.  With PG_STALE_RESET (online update only), a
