@@ -198,13 +198,15 @@ def _gpu_records(scene, g, p, spp, view):
 
 
 @pytest.mark.parametrize("W,H", [(64, 64), (67, 45), (1, 1), (5, 90)])
-@pytest.mark.parametrize("spp", [1, 4, 5, 8])
+@pytest.mark.parametrize("spp", [1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("kreg", ["new", "random_new", "mixed", "saturated"])
 def test_em_parity_same_input(W, H, spp, kreg):
     """One EM update from the same state and the same records.  "new" is the
     state every model starts from (k = 0 after a reset); the other regimes are
-    random states, whose narrow lobes may sit far from the samples.  spp 5
-    and 8 run the library's default tiles above spp 4 (16x16, 16x8)."""
+    random states, whose narrow lobes may sit far from the samples.  Every
+    spp runs the library's default tile: one pass up to spp 3, from spp 4 the
+    two-pass tile (16x16), whose split of the sample planes is uneven at odd
+    spp (spp 7: four planes, then three)."""
     say(f"case: em {W}x{H} spp {spp} {kreg}")
     seed = 5000 + W + 7 * H + spp
     scene = wl.make_scene(W, H, seed)
@@ -235,7 +237,7 @@ def test_em_parity_same_input(W, H, spp, kreg):
     say(f"  {st}  evidence-underflow pixels: {int(uf.sum())}")
 
 
-@pytest.mark.parametrize("spp", [1, 2, 4, 8])
+@pytest.mark.parametrize("spp", [1, 2, 3, 4, 5, 7, 8])
 def test_em_tile_shapes_bitwise_identical(spp):
     """Every built training tile gives the same bits (above spp 1 the tiles
     whose LDS would exceed 64 KiB are refused with PG_ERR_UNSUPPORTED)."""
