@@ -250,6 +250,10 @@ __device__ __forceinline__ void sample_pixel(const ParamsK &P, const ViewK &v, c
       const float zeta = u24(w4.x), xl = u24(w4.y), x1 = u24(w4.z), x2 = u24(w4.w);
       float sn, cs;
       sincospi_small(2.0f * x2, &sn, &cs);
+      // the guided and the cosine draws take p_b from the direction, after
+      // the branches, so that a wave whose lanes took both evaluates it once
+      bool pb_dir = false;
+      float pgz = 0.0f;  // the Gaussian density of a guided draw, from z
       if (zeta < pe) {
         // -2 ln(1 - x1) = -2 ln2 log2(1 - x1); 1 - x1 >= 2^-24 is normal
         const float rho = fsqrt(-1.38629436f * __builtin_amdgcn_logf(1.0f - x1));
@@ -258,49 +262,48 @@ __device__ __forceinline__ void sample_pixel(const ParamsK &P, const ViewK &v, c
         const float uy = fmaf(G.l22, z2, fmaf(G.l21, z1, G.my));
         if (ux >= 0.0f && ux <= 1.0f && uy >= 0.0f && uy <= 1.0f) {
           l = sq2hemi(ux, uy);
-          const float pg = G.norm * __builtin_amdgcn_exp2f(-0.72134752f * fmaf(z1, z1, z2 * z2));
-          pb = l.z > 0.0f ? brdf_pdf_only(px, l) : 0.0f;
-          D = fmaf(pe, pg, (1.0f - pe) * pb);
+          pgz = G.norm * __builtin_amdgcn_exp2f(-0.72134752f * fmaf(z1, z1, z2 * z2));
+          pb_dir = l.z > 0.0f;
           code = 2;
         } else {
           code = 3;
         }
-      } else {
-        bool ok;
-        if (xl < P.s_d) {
-          const float r = fsqrt(x1);
-          l = V3{r * cs, r * sn, fsqrt(1.0f - x1)};
-          ok = l.z > 0.0f;
-          if (ok) pb = brdf_pdf_only(px, l);
-        } else {
-          // x1 <= 1 - 2^-24, so 1 - x1 and t2 (0 or >= alpha^2 2^-24) are normal
-          const float t2 = px.alpha2 * x1 * frcp(1.0f - x1);
-          const float ch = __builtin_amdgcn_rsqf(1.0f + t2);
-          const float sh = fsqrt(t2) * ch;
-          const V3 h = V3{sh * cs, sh * sn, ch};
-          const float woh = dot3(px.wo, h);
-          l = V3{2.0f * woh * h.x - px.wo.x, 2.0f * woh * h.y - px.wo.y, 2.0f * woh * h.z - px.wo.z};
-          ok = l.z > 0.0f && woh > 0.0f;
-          if (ok) {
-            // GGX density of the drawn normal in closed form of xi_1:
-            // D(h) = (1 - xi_1 (1 - alpha^2))^2 / (pi alpha^2)
-            const float q = fmaf(-x1, 1.0f - px.alpha2, 1.0f);
-            const float pggx = 0.25f * kInvPi * q * q * ch * frcp(px.alpha2 * woh);
-            pb = fmaf(px.s_d * kInvPi, l.z, (1.0f - px.s_d) * pggx);
-          }
-        }
+      } else if (xl < P.s_d) {
+        const float r = fsqrt(x1);
+        l = V3{r * cs, r * sn, fsqrt(1.0f - x1)};
+        pb_dir = l.z > 0.0f;
+        code = pb_dir ? 1 : 4;
+      }
+      if (pb_dir) pb = brdf_pdf_only(px, l);
+      if (code == 2) {
+        D = fmaf(pe, pgz, (1.0f - pe) * pb);
+      } else if (code == 0) {
+        // the GGX draw (the only strategy left without a code)
+        // x1 <= 1 - 2^-24, so 1 - x1 and t2 (0 or >= alpha^2 2^-24) are normal
+        const float t2 = px.alpha2 * x1 * frcp(1.0f - x1);
+        const float ch = __builtin_amdgcn_rsqf(1.0f + t2);
+        const float sh = fsqrt(t2) * ch;
+        const V3 h = V3{sh * cs, sh * sn, ch};
+        const float woh = dot3(px.wo, h);
+        l = V3{2.0f * woh * h.x - px.wo.x, 2.0f * woh * h.y - px.wo.y, 2.0f * woh * h.z - px.wo.z};
+        const bool ok = l.z > 0.0f && woh > 0.0f;
         if (ok) {
-          float pg = 0.0f;
-          if (pe > 0.0f) {
-            float ux, uy;
-            hemi2sq(l, ux, uy);
-            pg = gauss_pdf_fast(G, ux, uy);
-          }
-          D = fmaf(pe, pg, (1.0f - pe) * pb);
-          code = 1;
-        } else {
-          code = 4;
+          // GGX density of the drawn normal in closed form of xi_1:
+          // D(h) = (1 - xi_1 (1 - alpha^2))^2 / (pi alpha^2)
+          const float q = fmaf(-x1, 1.0f - px.alpha2, 1.0f);
+          const float pggx = 0.25f * kInvPi * q * q * ch * frcp(px.alpha2 * woh);
+          pb = fmaf(px.s_d * kInvPi, l.z, (1.0f - px.s_d) * pggx);
         }
+        code = ok ? 1 : 4;
+      }
+      if (code == 1) {  // a BRDF draw: the Gaussian's density from the direction
+        float pg = 0.0f;
+        if (pe > 0.0f) {
+          float ux, uy;
+          hemi2sq(l, ux, uy);
+          pg = gauss_pdf_fast(G, ux, uy);
+        }
+        D = fmaf(pe, pg, (1.0f - pe) * pb);
       }
     }
     V3 w = V3{0.0f, 0.0f, 0.0f};
