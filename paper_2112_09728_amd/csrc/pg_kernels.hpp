@@ -679,6 +679,45 @@ __device__ __forceinline__ float4 list_record(const float4 *lds, uint32_t off) {
   return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(lds) + off);
 }
 
+// Calls f on the staged records of n list entries of one pixel, at rows
+// j0, j0 + step, ... of its column (column `me` of the [rows][nt] list
+// area).  AHEAD = 0: one record at a time (its entry's and its own LDS
+// reads wait in turn); AHEAD = 1: the next record is read from LDS before
+// f runs on the current one (its entry's read still waits); AHEAD = 2: the
+// next record and the entry after it, so both dependent LDS reads of a
+// visit pass during the previous visits' arithmetic (four more registers).
+// Reads past the last entry repeat the last entry (always a staged record).
+template <int AHEAD, typename F>
+__device__ __forceinline__ void for_each_record(const float4 *rec, const uint16_t *list, int nt, int me, int j0,
+                                                int step, int n, F &&f) {
+  static_assert(AHEAD >= 0 && AHEAD <= 2, "look-ahead of at most two records");
+  if (n <= 0) return;
+  const uint16_t *col = list + me;
+  if (AHEAD == 0) {
+    for (int i = 0; i < n; ++i) f(list_record(rec, col[(j0 + step * i) * nt]));
+    return;
+  }
+  const int last = n - 1;
+  auto entry = [&](int i) { return (uint32_t)col[(j0 + step * min(i, last)) * nt]; };
+  float4 r0 = list_record(rec, entry(0));
+  if (AHEAD == 1) {
+    for (int i = 0; i < n; ++i) {
+      const float4 r1 = list_record(rec, entry(i + 1));
+      f(r0);
+      r0 = r1;
+    }
+  } else {
+    uint32_t off1 = entry(1);
+    for (int i = 0; i < n; ++i) {
+      const uint32_t off2 = entry(i + 2);
+      const float4 r1 = list_record(rec, off1);
+      f(r0);
+      r0 = r1;
+      off1 = off2;
+    }
+  }
+}
+
 // Training list of one pixel: the LDS byte offsets of its kept candidates, in the
 // order of the training set (own samples by sample index, then picks by pick
 // index), stored in column `col` of the list area.  A candidate is kept when
@@ -876,9 +915,9 @@ __device__ __forceinline__ void em_load(const ViewK &v, const SamplesK &S, const
 // Dynamic LDS: records [spp][SH][SW] float4, then lists [spp + 20][NT]
 // uint16, then the pick table [48 spp] int16; the write-back reuses the area
 // ([8][NT] float).
-template <typename TG, int TW, int TH, bool STALE = false>
+template <typename TG, int TW, int TH, bool STALE = false, bool BATCH = false>
 __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const SamplesK &S, TG *gamma,
-                                        int iterations, int batch, int tx0, int ty0, int rot, float4 *lds,
+                                        int iterations, int tx0, int ty0, int rot, float4 *lds,
                                         EmShared<TW * TH> &sh, const EmInput<TW, TH> &R) {
   constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH, NT = TW * TH, IT = EmInput<TW, TH>::IT;
   uint16_t *list = reinterpret_cast<uint16_t *>(lds + S.spp * SA);
@@ -934,18 +973,20 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
   if (me_in) gamma_load(gamma, plane, idx, g);
   if (len > 0) {
     c.px = make_pixel(P, load3(v.n, plane, idx), load3(v.o, plane, idx), at(v.rough, idx), at(v.alb, idx));
-    if (STALE && !batch && g[7] >= 1.0f && stale_history(P, c.px, g, lds, list, me, len, NT)) gamma_reset(P, g);
+    if (STALE && !BATCH && g[7] >= 1.0f && stale_history(P, c.px, g, lds, list, me, len, NT)) gamma_reset(P, g);
   }
   if (len > 0) {  // otherwise no training sample (or no pixel): the model stays as it is
-    const int iters = batch ? iterations : 1;
+    const int iters = BATCH ? iterations : 1;
     for (int it = 0; it < iters; ++it) {
       c.T = lobe_term(gauss_setup(g[0], g[1], g[2], g[3], g[4], P.eps), g[5]);
       c.pi = g[5];
       Accum a = {0, 0, 0, 0, 0, 0, 0};
-      for (int j = 0; j < len; ++j) em_visit(c, list_record(lds, list[j * NT + me]), a);
+      // one record at a time: at 8 waves per SIMD the other waves cover the
+      // LDS latency, and a look-ahead's index arithmetic measured 3% slower
+      for_each_record<0>(lds, list, NT, me, 0, 1, len, [&](float4 r) { em_visit(c, r, a); });
       if (!(a.B0 > 0.0f)) break;
       accum_to_unit(a, c.T);
-      if (!batch) {
+      if (!BATCH) {
         em_merge_online(P, g, a);
       } else {
         if (a.B1 > 0.0f) {
@@ -1146,7 +1187,10 @@ __device__ __forceinline__ void em_tile2(const ParamsK &P, const ViewK &v, const
     }
     sh.work[pa] = (uint8_t)len;
     work0[pa] = (uint8_t)n0;
-    me = balance<NT>(len, pa, sh.cnt[1], sh.perm, rot + 1);
+    // each pass lasts as long as its longest list in the wave, so the lanes
+    // are grouped by the longer of their two parts (max(n0) + max(n1) per
+    // wave), not by the whole list
+    me = balance<NT>(max(n0, len - n0), pa, sh.cnt[1], sh.perm, rot + 1);
   }
   const int len = sh.work[me], n0 = work0[me];
   float g[8];
@@ -1162,7 +1206,7 @@ __device__ __forceinline__ void em_tile2(const ParamsK &P, const ViewK &v, const
     c.px = make_pixel(P, load3(v.n, plane, idx), load3(v.o, plane, idx), at(v.rough, idx), at(v.alb, idx));
     c.T = lobe_term(gauss_setup(g[0], g[1], g[2], g[3], g[4], P.eps), g[5]);
     c.pi = g[5];
-    for (int j = 0; j < n0; ++j) em_visit(c, list_record(rec, list[j * NT + me]), a);
+    for_each_record<2>(rec, list, NT, me, 0, 1, n0, [&](float4 r) { em_visit(c, r, a); });
   }
   __syncthreads();  // the first planes' records are no longer read
   stage2<TW, TH>(v, S, rec, vb, tx0, ty0, pg, spp, 0, false);
@@ -1172,7 +1216,7 @@ __device__ __forceinline__ void em_tile2(const ParamsK &P, const ViewK &v, const
     c.px = make_pixel(P, load3(v.n, plane, idx), load3(v.o, plane, idx), at(v.rough, idx), at(v.alb, idx));
     c.T = lobe_term(gauss_setup(g[0], g[1], g[2], g[3], g[4], P.eps), g[5]);
     c.pi = g[5];
-    for (int j = cap - 1; j >= cap - (len - n0); --j) em_visit(c, list_record(rec, list[j * NT + me]), a);
+    for_each_record<2>(rec, list, NT, me, cap - 1, -1, len - n0, [&](float4 r) { em_visit(c, r, a); });
     if (a.B0 > 0.0f) {  // otherwise no weight: the model stays as it is
       accum_to_unit(a, c.T);
       em_merge_online(P, g, a);
@@ -1197,9 +1241,9 @@ __device__ __forceinline__ void em_tile2(const ParamsK &P, const ViewK &v, const
 // loads of one block behind the arithmetic of the others better than a
 // persistent loop with register prefetch.
 // TWO: the two-pass tile (online EM above spp 1; em2_lds_front).
-template <typename TG, int TW, int TH, bool STALE, bool TWO = false>
-__global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(8))) void k_em(ParamsK P, ViewK v, SamplesK S, TG *__restrict__ gamma,
-                                               int iterations, int batch, int tiles_x, int n_tiles) {
+template <typename TG, int TW, int TH, bool STALE, bool TWO = false, bool BATCH = false>
+__global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TWO ? 5 : 8))) void k_em(ParamsK P, ViewK v, SamplesK S, TG *__restrict__ gamma,
+                                               int iterations, int tiles_x, int n_tiles) {
   extern __shared__ float4 lds[];  // records, lists and the pick table (em_lds_front, em2_lds_front)
   __shared__ EmShared<TW * TH> sh;
   const int tile = xcd_tile(blockIdx.x, n_tiles);
@@ -1210,7 +1254,7 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(8))) voi
   if (TWO)
     em_tile2<TG, TW, TH>(P, v, S, gamma, tx0, ty0, (int)blockIdx.x, lds, sh, R);
   else
-    em_tile<TG, TW, TH, STALE>(P, v, S, gamma, iterations, batch, tx0, ty0, (int)blockIdx.x, lds, sh, R);
+    em_tile<TG, TW, TH, STALE, BATCH>(P, v, S, gamma, iterations, tx0, ty0, (int)blockIdx.x, lds, sh, R);
 }
 
 // ---------------------------------------------------------------------------
@@ -1408,7 +1452,7 @@ __global__ __launch_bounds__(256) void k_rs_batched(const char *__restrict__ tab
 // class differs from the launch (tile, spp, dtype, or more tiles than the
 // grid) is not processed.
 template <typename TG, int TW, int TH, bool TWO>
-__global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TH == 2 ? 1 : 8))) void k_em_batched(const char *__restrict__ table, int dtype, int cls,
+__global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TH == 2 ? 1 : (TWO ? 5 : 8)))) void k_em_batched(const char *__restrict__ table, int dtype, int cls,
                                                        int spp_cap) {
   extern __shared__ float4 lds[];  // sized for spp_cap (em_lds_front, em2_lds_front)
   __shared__ EmShared<TW * TH> sh;
@@ -1433,7 +1477,7 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TH == 2 
   if (TWO)
     em_tile2<TG, TW, TH>(P, bv.cur, bv.S, (TG *)bv.gout, tx0, ty0, (int)blockIdx.x, lds, sh, R);
   else
-    em_tile<TG, TW, TH>(P, bv.cur, bv.S, (TG *)bv.gout, 1, 0, tx0, ty0, (int)blockIdx.x, lds, sh, R);
+    em_tile<TG, TW, TH>(P, bv.cur, bv.S, (TG *)bv.gout, 1, tx0, ty0, (int)blockIdx.x, lds, sh, R);
 }
 
 // Philox words for given counters (diagnostic entry).

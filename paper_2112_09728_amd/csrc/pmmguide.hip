@@ -221,12 +221,14 @@ pg_status launch_em_t(const ParamsK &P, const ViewK &v, const SamplesK &S, TG *g
   const bool two = em_two_pass(S.spp, batch, P.flags);
   const size_t lds = tile_lds(Tile{TW, TH}, S.spp, two);
   if (two)
-    hipLaunchKernelGGL((k_em<TG, TW, TH, false, true>), dim3(n), dim3(TW * TH), lds, st, P, v, S, g, iters, batch,
+    hipLaunchKernelGGL((k_em<TG, TW, TH, false, true>), dim3(n), dim3(TW * TH), lds, st, P, v, S, g, iters, tx, n);
+  else if (batch)
+    hipLaunchKernelGGL((k_em<TG, TW, TH, false, false, true>), dim3(n), dim3(TW * TH), lds, st, P, v, S, g, iters,
                        tx, n);
-  else if ((P.flags & kStaleReset) && !batch)
-    hipLaunchKernelGGL((k_em<TG, TW, TH, true>), dim3(n), dim3(TW * TH), lds, st, P, v, S, g, iters, batch, tx, n);
+  else if (P.flags & kStaleReset)
+    hipLaunchKernelGGL((k_em<TG, TW, TH, true>), dim3(n), dim3(TW * TH), lds, st, P, v, S, g, iters, tx, n);
   else
-    hipLaunchKernelGGL((k_em<TG, TW, TH, false>), dim3(n), dim3(TW * TH), lds, st, P, v, S, g, iters, batch, tx, n);
+    hipLaunchKernelGGL((k_em<TG, TW, TH, false>), dim3(n), dim3(TW * TH), lds, st, P, v, S, g, iters, tx, n);
   return PG_OK;
 }
 
