@@ -981,9 +981,14 @@ __device__ __forceinline__ void em_tile(const ParamsK &P, const ViewK &v, const 
       c.T = lobe_term(gauss_setup(g[0], g[1], g[2], g[3], g[4], P.eps), g[5]);
       c.pi = g[5];
       Accum a = {0, 0, 0, 0, 0, 0, 0};
-      // one record at a time: at 8 waves per SIMD the other waves cover the
-      // LDS latency, and a look-ahead's index arithmetic measured 3% slower
-      for_each_record<0>(lds, list, NT, me, 0, 1, len, [&](float4 r) { em_visit(c, r, a); });
+      // at spp 1 one record at a time: 8 waves per SIMD cover the LDS
+      // latency, and a look-ahead's index arithmetic measured 3% slower;
+      // above, the staged records leave 4-5 waves and the reads go ahead
+      // (batch EM, with more state live, keeps one record at a time)
+      if (!BATCH && S.spp > 1)
+        for_each_record<2>(lds, list, NT, me, 0, 1, len, [&](float4 r) { em_visit(c, r, a); });
+      else
+        for_each_record<0>(lds, list, NT, me, 0, 1, len, [&](float4 r) { em_visit(c, r, a); });
       if (!(a.B0 > 0.0f)) break;
       accum_to_unit(a, c.T);
       if (!BATCH) {
