@@ -118,7 +118,7 @@ def parse():
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
+        print(f"bench.py: libpmmguide runs on one GPU; --gpus {a.gpus} is not supported "
               "(the design for several GPUs is described, not built).", file=sys.stderr)
         sys.exit(2)
     import torch
