@@ -119,7 +119,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py: libpmmguide runs on one GPU; --gpus {a.gpus} is not supported "
-              "(the design for several GPUs is described, not built).", file=sys.stderr)
+              "(sharding across GPUs is designed, not implemented).", file=sys.stderr)
         sys.exit(2)
     import torch
 
