@@ -481,8 +481,11 @@ __device__ __forceinline__ void lobes_update(const ParamsK &P, const ViewK &v, i
 // With VPL, positions [3][H*pitch] and hit distances [spp][H*pitch] give the
 // positional reuse of virtual point lights (the training directions of every
 // pixel are re-derived from the staged y).
+// Two lobes (directional) fit 72 VGPRs without spilling, 7 waves per SIMD
+// instead of the 6 that the compiler's own choice (75) leaves: EM -4%; at
+// 8 waves, or with VPL at 7, it spills.
 template <int K, int TW, int TH, bool VPL = false>
-__global__ __launch_bounds__(TW *TH) void k_lobes_em(ParamsK P, ViewK v, SamplesK S, float *__restrict__ gamma,
+__global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(K == 2 && !VPL ? 7 : 1))) void k_lobes_em(ParamsK P, ViewK v, SamplesK S, float *__restrict__ gamma,
                                                      int tiles_x, int n_tiles, const float *__restrict__ pos,
                                                      const float *__restrict__ hit) {
   constexpr int SW = TW + 2 * kR, SH = TH + 2 * kR, SA = SW * SH, NT = TW * TH;
